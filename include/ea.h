@@ -1,0 +1,206 @@
+/*
+ * ea.h -- C ABI of the MI355X (gfx950) engine for Metropolis Monte Carlo with
+ * parallel tempering on the three-dimensional Edwards-Anderson spin glass in a
+ * uniform field (arXiv:1403.4560).
+ *
+ * The model is the Hamiltonian of eq. 1, H = -sum_<ij> J_ij S_i S_j - h sum_i S_i,
+ * on a periodic simple cubic lattice of N = L^3 Ising spins (Methods).  Each
+ * disorder sample ("sample") is simulated as two independent replicas
+ * ("chains" a and b) at each of N_T temperatures, coupled only by parallel
+ * tempering within a chain (Methods, parallel tempering paragraph).  The
+ * library measures the two-replica overlap q(k) of eq. 2 at k = 0, at the three
+ * axis vectors (2pi/L)e_d and at the six images of (2pi/L, 2pi/L, 0), and
+ * accumulates the moments from which eqs. 3-6 (Binder ratio, chi(k), xi_L,
+ * R12) follow (ea_finalize).
+ *
+ * Numeric contract (every result is bit-reproducible; see the oracle tests):
+ *   site i = x + L(y + Lz), parity p = (x+y+z)&1, sublattice index h = i>>1;
+ *   bond J_d[i] joins site i and site i + e_d (periodic), d = 0,1,2 = x,y,z.
+ *   A sweep is: every parity-0 site of every walker, then every parity-1
+ *   site (Metropolis, "checkerboard"), then one replica-exchange pass per
+ *   chain over pairs (t,t+1) with t = n&1, n&1+2, ..., then a measurement if
+ *   one is due.  Random numbers come from Philox4x32-10 (Salmon et al., SC'11)
+ *   keyed by seed and addressed by (h>>2, 2n+p, (purpose<<28)|(t<<1)|r,
+ *   sample_id); they depend on the temperature slot t, never on where a
+ *   walker's spins live, so results do not depend on the launch plan.
+ *   Local fields and the acceptance test are binary32 with an in-house
+ *   exponential (exact on the 2^-18 coupling grid); energies are exact
+ *   (integer units) and exchange probabilities and all accumulators binary64.
+ *
+ * Conventions for every entry point:
+ *   - returns EA_OK (0) or a negative ea_status; no C++ exception crosses.
+ *   - on failure, ea_last_error() returns a thread-local message.
+ *   - pointers named *_host are host memory owned by the caller; the library
+ *     copies what it needs before returning (create, write_state) or fills
+ *     caller-allocated buffers of the documented size (measure, read_state).
+ *   - device memory is owned by the ensemble and freed by ea_destroy.
+ *   - after EA_EDEVICE the handle rejects every call but ea_destroy
+ *     (EA_ESTATE).  A handle is not thread-safe.
+ */
+#ifndef EA_H
+#define EA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ea_ensemble ea_ensemble;
+
+typedef enum {
+    EA_OK = 0,
+    EA_EINVAL = -1,       /* invalid argument (message says which)              */
+    EA_ENOMEM = -2,       /* device or host allocation failed                    */
+    EA_EDEVICE = -3,      /* a HIP call failed; the handle is now unusable      */
+    EA_ESTATE = -4,       /* handle unusable, or tracked state inconsistent     */
+    EA_EUNSUPPORTED = -5  /* valid but not supported (e.g. odd L)               */
+} ea_status;
+
+enum { EA_J_GAUSS_F32 = 0, EA_J_PM1_I8 = 1 };
+
+/* Accumulators per (sample, slot), binary64, summed over measurements:
+ *   [0] n            [1..4] sum of q0, q0^2, q0^3, q0^4 (q0 = q(k=0), eq. 2)
+ *   [5+3f], [6+3f], [7+3f]: sum of Re q(k_f), Im q(k_f), |q(k_f)|^2 for
+ *     f = 0,1,2: k = (2pi/L) e_x, e_y, e_z;
+ *     f = 3..8: k = (2pi/L) (1,1,0), (1,-1,0), (1,0,1), (1,0,-1), (0,1,1),
+ *     (0,1,-1)
+ *   [32], [33]: sum of E, E^2 of chain a's walker at the slot;
+ *   [34], [35]: the same for chain b.                                      */
+enum { EA_NACC = 36, EA_NPLANE = 9 };
+
+/* Input description for ea_create_ensemble.  All arrays are host memory in
+ * sample-concatenated order; n_T and L may differ between samples. */
+typedef struct {
+    int32_t n_samples;           /* S >= 1                                      */
+    const uint32_t *sample_id;   /* [S] Philox address word 3; NULL => 0..S-1   */
+    const int32_t *L;            /* [S] even, 2 <= L <= 64                      */
+    const int32_t *n_temps;      /* [S] 1 <= n_T <= 64                          */
+    const double *beta;          /* concat [S][n_T]: finite, > 0, non-decreasing */
+    const float *h;              /* [S] uniform field, finite                    */
+    int32_t jkind;               /* EA_J_GAUSS_F32 or EA_J_PM1_I8                */
+    const void *J;               /* concat [S][3][N]: float on the 2^-18 grid
+                                    with |J| < 8, or int8 +-1                    */
+    const int8_t *spins0;        /* concat [S][2][n_T][N], values +-1, walker w
+                                    starts at slot w                             */
+    uint64_t seed;               /* Philox key: k0 = low, k1 = high 32 bits     */
+    int32_t measure_every;       /* m >= 1, or 0 = never measure                */
+    int64_t measure_start;       /* measure after sweep n iff n+1 > start and
+                                    (n+1-start) % m == 0                         */
+} ea_desc;
+
+/* Launch plan.  Every plan gives bit-identical results. */
+typedef struct {
+    int32_t chunk;      /* sweeps per persistent launch (>= 1)                  */
+    int32_t threads;    /* threads per workgroup: 256, 512 or 1024              */
+    int32_t use_graph;  /* 1: replay each chunk from a captured hipGraph       */
+    int32_t reserved;
+} ea_plan;
+
+/* Create an ensemble from a description, copy it to the device and bind it
+ * to a HIP stream (NULL: the null stream).  *out is NULL on failure.
+ * Errors: EA_EINVAL for a malformed description (odd or out-of-range L,
+ * spins not +-1, couplings off their alphabet, bad beta, bad m/start),
+ * EA_ENOMEM, EA_EDEVICE. */
+ea_status ea_create_ensemble(const ea_desc *desc, void *hip_stream, ea_ensemble **out);
+
+/* Advance every sample by n_sweeps sweeps (half-sweep p=0, half-sweep p=1,
+ * replica exchange, measurement if due; Methods).  Asynchronous on the bound
+ * stream; n_sweeps >= 0.  sweep_pt(a) then sweep_pt(b) equals sweep_pt(a+b)
+ * bit for bit. */
+ea_status ea_sweep_pt(ea_ensemble *ens, int64_t n_sweeps);
+
+/* The same computation, launched one sample at a time (two workgroups per
+ * launch) serially on the bound stream: the unbatched comparator.  Results
+ * are bit-identical to ea_sweep_pt. */
+ea_status ea_sweep_pt_unbatched(ea_ensemble *ens, int64_t n_sweeps);
+
+/* Copy the accumulators and counters to the host and synchronize.
+ * flags & EA_MEASURE_NOW first measures the current state once.
+ * acc_host   [S][n_T][36] (layout above; may be NULL)
+ * flips_host [S][2][n_T] accepted spin flips per (sample, chain, slot)
+ * swaps_host [S][2][n_T] accepted exchanges of pair (t, t+1) at index t      */
+enum { EA_MEASURE_NOW = 1 };
+ea_status ea_measure(ea_ensemble *ens, int32_t flags, double *acc_host,
+                     int64_t *flips_host, int64_t *swaps_host);
+
+/* Copy the state to the host and synchronize.  Any pointer may be NULL.
+ * spins_host      [S][2][n_T][N] int8 in slot order (index t holds the walker
+ *                 at slot t), natural site order
+ * walker_at_slot  [S][2][n_T]
+ * E_host          [S][2][n_T] total energy (eq. 1) of the walker at each slot
+ * sweep           sweeps completed                                         */
+ea_status ea_read_state(ea_ensemble *ens, int8_t *spins_host, int32_t *walker_at_slot,
+                        double *E_host, int64_t *sweep);
+
+/* Replace the state (resume from a checkpoint): spins in slot order as
+ * returned by ea_read_state, and the sweep counter.  Energies are recomputed
+ * on the device; walkers are renumbered so walker t sits at slot t, which
+ * changes no later result.  Accumulators and counters are left alone. */
+ea_status ea_write_state(ea_ensemble *ens, const int8_t *spins_host, int64_t sweep);
+
+/* Load accumulators and counters (any NULL is left alone); layouts as in
+ * ea_measure. */
+ea_status ea_load_accumulators(ea_ensemble *ens, const double *acc_host,
+                               const int64_t *flips_host, const int64_t *swaps_host);
+
+/* Zero accumulators and counters. */
+ea_status ea_reset_accumulators(ea_ensemble *ens);
+
+/* Recompute every walker's energy from its spins on the device and compare
+ * with the incrementally tracked value.  *mismatches = number of walkers
+ * that differ (0 for a consistent state).  Synchronizing. */
+ea_status ea_check_energies(ea_ensemble *ens, int64_t *mismatches);
+
+/* Disorder averages per temperature slot over the samples with lattice size
+ * L and n_T slots (eqs. 3-6), computed on the device from the accumulators.
+ * out_host [n_T][EA_NOBS] binary64, columns in ea_obs order.  Samples with
+ * other L or n_T are ignored; EA_EINVAL if none match. */
+enum {
+    EA_OBS_Q = 0,        /* [<q(0)>]                                          */
+    EA_OBS_CHI0,         /* chi(0) = N([<q^2>] - [<q>]^2)            eq. 4     */
+    EA_OBS_CHIKMIN,      /* chi at |k| = 2pi/L, mean of three axes   eq. 4     */
+    EA_OBS_CHIK2,        /* chi at (2pi/L)(1,1,0), mean of six images          */
+    EA_OBS_BINDER,       /* g of eq. 3, moments centred on [<q(0)>]            */
+    EA_OBS_XI,           /* xi_L of eq. 5                                      */
+    EA_OBS_R12,          /* chi(k1)/chi(k2) of eq. 6                           */
+    EA_OBS_RATIO,        /* chi(0)/chi(kmin)                                   */
+    EA_OBS_EA,           /* [<E>] chain a                                      */
+    EA_OBS_EB,           /* [<E>] chain b                                      */
+    EA_OBS_NSAMP,        /* number of samples averaged                         */
+    EA_NOBS
+};
+ea_status ea_finalize(ea_ensemble *ens, int32_t L, int32_t n_temps, double *out_host);
+
+/* Launch plan (see ea_plan); EA_EINVAL for values out of range. */
+ea_status ea_set_plan(ea_ensemble *ens, const ea_plan *plan);
+ea_status ea_get_plan(const ea_ensemble *ens, ea_plan *plan);
+
+/* Time candidate plans on a copy of the state (the ensemble's state and
+ * accumulators are restored afterwards) and keep the fastest.  Synchronizing.
+ * trial_sweeps >= 1. */
+ea_status ea_autotune(ea_ensemble *ens, int32_t trial_sweeps);
+
+/* Kernel timing on the bound stream: when enabled, every sweep-kernel launch
+ * is bracketed by HIP events; ea_kernel_time returns the summed duration in
+ * milliseconds and the number of launches since it was enabled (it
+ * synchronizes).  Graph replay is bypassed while timing is on. */
+ea_status ea_set_timing(ea_ensemble *ens, int32_t enable);
+ea_status ea_kernel_time(ea_ensemble *ens, double *ms_total, int64_t *launches);
+
+/* Block the host until all work on the bound stream has finished. */
+ea_status ea_synchronize(ea_ensemble *ens);
+
+/* Sizes: samples, total slots (sum n_T), device bytes held. */
+ea_status ea_query(const ea_ensemble *ens, int32_t *n_samples, int64_t *total_slots,
+                   int64_t *device_bytes);
+
+void ea_destroy(ea_ensemble *ens);
+const char *ea_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EA_H */

@@ -1,0 +1,110 @@
+// ea_device.hpp -- device primitives of the gfx950 engine: counter-based
+// random numbers and the in-house exponentials of the acceptance tests.
+//
+// Compiled with -ffp-contract=off: every floating-point operation below is one
+// IEEE operation rounded to nearest even, so the results are reproducible bit
+// for bit by any conforming implementation of the same steps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ea {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As Easy
+// as 1, 2, 3", SC'11).  Each of the ten rounds forms the 64-bit products of
+// counter words 0 and 2 with the two round multipliers; the new counter is
+// (hi(c2*M1) ^ c1 ^ k0, lo(c2*M1), hi(c0*M0) ^ c3 ^ k1, lo(c0*M0)).  The key
+// advances by the Weyl increments between rounds.
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += W0;
+        k1 += W1;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// Counter purposes (bits 28..31 of counter word 2).
+constexpr uint32_t PURPOSE_METROPOLIS = 0u;
+constexpr uint32_t PURPOSE_EXCHANGE = 1u;
+
+// e^x for -86 <= x <= 0 in binary32: Cody-Waite reduction x = k ln2 + r with
+// the split ln2 = C1 + C2 (C1 keeps 16 significant bits so k*C1 is exact for
+// |k| <= 255), then the degree-7 Taylor polynomial of e^r in Horner form and
+// an exact scaling by 2^k.  x < -86 gives 0.  Constants (IEEE binary32 bit
+// patterns): 1/ln2, ln2 rounded then its 8 low bits cleared, the rounded
+// remainder ln2 - C1, and the rounded reciprocal factorials 1/j!.
+__device__ __forceinline__ float exp_ea32(float x)
+{
+    const float LOG2E = __uint_as_float(0x3FB8AA3Bu);
+    const float C1 = __uint_as_float(0x3F317200u);
+    const float C2 = __uint_as_float(0x35BFBE8Eu);
+    const float xc = fmaxf(x, -100.0f);  // keeps k in range; result masked below
+    const float k = __builtin_rintf(xc * LOG2E);
+    const float r = (xc - k * C1) - k * C2;
+    float p = __uint_as_float(0x39500D01u);          // 1/7!
+    p = p * r + __uint_as_float(0x3AB60B61u);        // 1/6!
+    p = p * r + __uint_as_float(0x3C088889u);        // 1/5!
+    p = p * r + __uint_as_float(0x3D2AAAABu);        // 1/4!
+    p = p * r + __uint_as_float(0x3E2AAAABu);        // 1/3!
+    p = p * r + 0.5f;
+    p = p * r + 1.0f;
+    p = p * r + 1.0f;
+    const float v = __builtin_amdgcn_ldexpf(p, (int)k);
+    return x < -86.0f ? 0.0f : v;
+}
+
+// e^x for -700 <= x <= 0 in binary64, the same construction: C1 keeps 42
+// significant bits (11 low bits of fl64(ln2) cleared), degree-13 Taylor
+// polynomial with rounded 1/j!, x < -700 gives 0.
+__device__ __forceinline__ double exp_ea64(double x)
+{
+    const double LOG2E = __longlong_as_double(0x3FF71547652B82FEll);
+    const double C1 = __longlong_as_double(0x3FE62E42FEFA3800ll);
+    const double C2 = __longlong_as_double(0x3D2EF35793C76730ll);
+    const double xc = fmax(x, -800.0);
+    const double k = __builtin_rint(xc * LOG2E);
+    const double r = (xc - k * C1) - k * C2;
+    double p = __longlong_as_double(0x3DE6124613A86D09ll);        // 1/13!
+    p = p * r + __longlong_as_double(0x3E21EED8EFF8D898ll);       // 1/12!
+    p = p * r + __longlong_as_double(0x3E5AE64567F544E4ll);       // 1/11!
+    p = p * r + __longlong_as_double(0x3E927E4FB7789F5Cll);       // 1/10!
+    p = p * r + __longlong_as_double(0x3EC71DE3A556C734ll);       // 1/9!
+    p = p * r + __longlong_as_double(0x3EFA01A01A01A01All);       // 1/8!
+    p = p * r + __longlong_as_double(0x3F2A01A01A01A01All);       // 1/7!
+    p = p * r + __longlong_as_double(0x3F56C16C16C16C17ll);       // 1/6!
+    p = p * r + __longlong_as_double(0x3F81111111111111ll);       // 1/5!
+    p = p * r + __longlong_as_double(0x3FA5555555555555ll);       // 1/4!
+    p = p * r + __longlong_as_double(0x3FC5555555555555ll);       // 1/3!
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    const double v = __builtin_amdgcn_ldexp(p, (int)k);
+    return x < -700.0 ? 0.0 : v;
+}
+
+// 24-bit and 53-bit uniforms in [0, 1) from Philox output words.
+__device__ __forceinline__ float u24_of(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+__device__ __forceinline__ double u53_of(uint32_t w0, uint32_t w1)
+{
+    return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6)) * 0x1p-53;
+}
+
+}  // namespace ea

@@ -1,0 +1,900 @@
+// ea_host.cpp -- host side of the C ABI declared in include/ea.h.
+//
+// Owns the device buffers of an ensemble, converts between the caller's
+// natural site order and the device's sublattice-split layout, schedules the
+// chunked persistent launches (optionally replayed from a captured hipGraph),
+// and implements measurement, checkpoint and planning calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ea.h"
+#include "ea_types.hpp"
+
+namespace ea {
+template <int JK> __global__ void lds_sweep_kernel(SweepArgs A);
+__global__ void measure_kernel(MeasureArgs A);
+__global__ void advance_kernel(int64_t *state, int64_t k);
+template <int JK>
+__global__ void energy_kernel(const SampleDev *, const int32_t *, const int8_t *, const void *, int64_t *,
+                              int32_t *);
+__global__ void snapshot_kernel(const SampleDev *, const int32_t *, const int8_t *, const int32_t *,
+                                const int64_t *, const int32_t *, int, int8_t *, double *);
+__global__ void finalize_kernel(const SampleDev *, int, int, int, const double *, double *);
+}  // namespace ea
+
+using namespace ea;
+
+namespace {
+
+thread_local std::string g_err;
+
+ea_status fail(ea_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+struct SampleHost {
+    int L, nT, N;
+    uint32_t id;
+    float h;
+    int64_t spin_off, J_off;
+    int32_t slot_off;
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ea_ensemble {
+    int S = 0;
+    int jkind = 0;
+    uint64_t seed = 0;
+    int32_t m = 0;
+    int64_t mstart = 0;
+    std::vector<SampleHost> smp;
+    int64_t total_slots = 0, spin_bytes = 0, J_elems = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool dead = false;
+    int64_t sweep = 0;
+    ea_plan plan{};
+    size_t lds_needed = 0;
+    int device = 0;
+    // device buffers
+    DevBuf samples, items, spins, J, beta, beta32, lut, was, EJ, M, flips, swaps, acc, frames, frameE,
+        state, slot_sample, costab, sintab, scratchE, scratchM, finout;
+    int64_t frames_cap = 0;  // frames allocated
+    std::map<int, hipGraphExec_t> graphs;
+    std::map<int, hipGraph_t> graph_defs;
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+    int64_t device_bytes = 0;
+};
+
+namespace {
+
+#define HIP_TRY(ens, call)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            if (ens) (ens)->dead = true;                                                        \
+            return fail(EA_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));             \
+        }                                                                                       \
+    } while (0)
+
+ea_status dalloc(ea_ensemble *e, DevBuf &b, size_t bytes)
+{
+    b.bytes = bytes;
+    if (bytes == 0) {
+        b.p = nullptr;
+        return EA_OK;
+    }
+    hipError_t st = hipMalloc(&b.p, bytes);
+    if (st != hipSuccess) {
+        b.p = nullptr;
+        return fail(EA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(st));
+    }
+    e->device_bytes += (int64_t)bytes;
+    return EA_OK;
+}
+
+void dfree(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+int parity(int L, int i) { return (i % L + (i / L) % L + i / (L * L)) & 1; }
+
+bool usable(const ea_ensemble *e)
+{
+    if (!e) {
+        fail(EA_EINVAL, "null ensemble");
+        return false;
+    }
+    if (e->dead) {
+        fail(EA_ESTATE, "ensemble unusable after an earlier device error");
+        return false;
+    }
+    return true;
+}
+
+ea_status validate(const ea_desc *d)
+{
+    if (!d) return fail(EA_EINVAL, "desc is NULL");
+    if (d->n_samples < 1) return fail(EA_EINVAL, "n_samples must be >= 1");
+    if (!d->L || !d->n_temps || !d->beta || !d->h || !d->J || !d->spins0)
+        return fail(EA_EINVAL, "L, n_temps, beta, h, J and spins0 are required");
+    if (d->jkind != EA_J_GAUSS_F32 && d->jkind != EA_J_PM1_I8) return fail(EA_EINVAL, "unknown jkind %d", d->jkind);
+    if (d->measure_every < 0) return fail(EA_EINVAL, "measure_every must be >= 0");
+    if (d->measure_start < 0) return fail(EA_EINVAL, "measure_start must be >= 0");
+    int64_t boff = 0, joff = 0, soff = 0;
+    for (int s = 0; s < d->n_samples; ++s) {
+        const int L = d->L[s], nT = d->n_temps[s];
+        if (L < 2 || L > MAX_L) return fail(EA_EINVAL, "sample %d: L=%d outside [2, %d]", s, L, MAX_L);
+        if (L & 1) return fail(EA_EUNSUPPORTED, "sample %d: odd L=%d (the checkerboard needs even L)", s, L);
+        if (nT < 1 || nT > MAX_T) return fail(EA_EINVAL, "sample %d: n_temps=%d outside [1, %d]", s, nT, MAX_T);
+        if (!std::isfinite(d->h[s])) return fail(EA_EINVAL, "sample %d: h not finite", s);
+        for (int t = 0; t < nT; ++t) {
+            const double b = d->beta[boff + t];
+            if (!std::isfinite(b) || b <= 0.0) return fail(EA_EINVAL, "sample %d: beta[%d] not finite and > 0", s, t);
+            if (t > 0 && b < d->beta[boff + t - 1])
+                return fail(EA_EINVAL, "sample %d: beta must be non-decreasing", s);
+        }
+        const int64_t N = (int64_t)L * L * L;
+        for (int64_t i = 0; i < 3 * N; ++i) {
+            if (d->jkind == EA_J_GAUSS_F32) {
+                const float v = ((const float *)d->J)[joff + i];
+                const float u = v * 262144.0f;
+                if (!std::isfinite(v) || std::fabs(v) >= 8.0f || u != std::nearbyint(u))
+                    return fail(EA_EINVAL, "sample %d: coupling %lld not on the 2^-18 grid with |J| < 8", s,
+                                (long long)i);
+            } else {
+                const int8_t v = ((const int8_t *)d->J)[joff + i];
+                if (v != 1 && v != -1) return fail(EA_EINVAL, "sample %d: coupling %lld not +-1", s, (long long)i);
+            }
+        }
+        for (int64_t i = 0; i < 2 * nT * N; ++i) {
+            const int8_t v = d->spins0[soff + i];
+            if (v != 1 && v != -1) return fail(EA_EINVAL, "sample %d: spin %lld not +-1", s, (long long)i);
+        }
+        boff += nT;
+        joff += 3 * N;
+        soff += 2 * nT * N;
+    }
+    return EA_OK;
+}
+
+size_t max_lds_bytes()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+    return (size_t)v;
+}
+
+void destroy_all(ea_ensemble *e)
+{
+    if (!e) return;
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : e->graph_defs) (void)hipGraphDestroy(kv.second);
+    for (auto &p : e->ev_used) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    for (auto &p : e->ev_free) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    DevBuf *bufs[] = {&e->samples, &e->items, &e->spins, &e->J, &e->beta, &e->beta32, &e->lut,
+                      &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->frames,
+                      &e->frameE, &e->state, &e->slot_sample, &e->costab, &e->sintab,
+                      &e->scratchE, &e->scratchM, &e->finout};
+    for (DevBuf *b : bufs) dfree(*b);
+    if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+// Snapshot frames needed by a chunk of K sweeps (at most ceil(K/m) + 1).
+int64_t frames_for_chunk(const ea_ensemble *e, int K)
+{
+    if (e->m <= 0) return 1;
+    return (int64_t)K / e->m + 2;
+}
+
+ea_status ensure_frames(ea_ensemble *e, int K)
+{
+    const int64_t need = frames_for_chunk(e, K);
+    if (need <= e->frames_cap) return EA_OK;
+    (void)hipStreamSynchronize(e->stream);
+    for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : e->graph_defs) (void)hipGraphDestroy(kv.second);
+    e->graphs.clear();
+    e->graph_defs.clear();
+    e->device_bytes -= (int64_t)(e->frames.bytes + e->frameE.bytes);
+    dfree(e->frames);
+    dfree(e->frameE);
+    ea_status st = dalloc(e, e->frames, (size_t)(need * e->spin_bytes));
+    if (st) return st;
+    st = dalloc(e, e->frameE, (size_t)(need * 2 * e->total_slots) * sizeof(double));
+    if (st) return st;
+    e->frames_cap = need;
+    return EA_OK;
+}
+
+SweepArgs sweep_args(const ea_ensemble *e, int K, const int32_t *items, int n_items)
+{
+    SweepArgs A{};
+    A.samples = (const SampleDev *)e->samples.p;
+    A.items = items;
+    A.n_items = n_items;
+    A.K = K;
+    A.spins = (int8_t *)e->spins.p;
+    A.J = e->J.p;
+    A.beta = (const double *)e->beta.p;
+    A.beta32 = (const float *)e->beta32.p;
+    A.lut = (const uint32_t *)e->lut.p;
+    A.was = (int32_t *)e->was.p;
+    A.EJ = (int64_t *)e->EJ.p;
+    A.M = (int32_t *)e->M.p;
+    A.flips = (int64_t *)e->flips.p;
+    A.swaps = (int64_t *)e->swaps.p;
+    A.frames = (int8_t *)e->frames.p;
+    A.frameE = (double *)e->frameE.p;
+    A.frame_bytes = e->spin_bytes;
+    A.total_slots = e->total_slots;
+    A.state = (const int64_t *)e->state.p;
+    A.key0 = (uint32_t)e->seed;
+    A.key1 = (uint32_t)(e->seed >> 32);
+    A.measure_every = e->m;
+    A.measure_start = e->mstart;
+    return A;
+}
+
+MeasureArgs measure_args(const ea_ensemble *e, int K, int explicit_frames)
+{
+    MeasureArgs M{};
+    M.samples = (const SampleDev *)e->samples.p;
+    M.slot_sample = (const int32_t *)e->slot_sample.p;
+    M.frames = (const int8_t *)e->frames.p;
+    M.frameE = (const double *)e->frameE.p;
+    M.frame_bytes = e->spin_bytes;
+    M.total_slots = e->total_slots;
+    M.acc = (double *)e->acc.p;
+    M.costab = (const double *)e->costab.p;
+    M.sintab = (const double *)e->sintab.p;
+    M.state = (const int64_t *)e->state.p;
+    M.K = K;
+    M.explicit_frames = explicit_frames;
+    M.measure_every = e->m;
+    M.measure_start = e->mstart;
+    return M;
+}
+
+hipError_t launch_sweep(ea_ensemble *e, int K, const int32_t *items, int n_items)
+{
+    SweepArgs A = sweep_args(e, K, items, n_items);
+    dim3 grid(n_items), block(e->plan.threads);
+    if (e->jkind == EA_J_GAUSS_F32)
+        hipLaunchKernelGGL(lds_sweep_kernel<0>, grid, block, e->lds_needed, e->stream, A);
+    else
+        hipLaunchKernelGGL(lds_sweep_kernel<1>, grid, block, e->lds_needed, e->stream, A);
+    return hipGetLastError();
+}
+
+// One chunk: the sweep kernel(s), the measurement of the chunk's frames and
+// the advance of the device sweep counter.  unbatched: one launch per sample.
+hipError_t enqueue_chunk(ea_ensemble *e, int K, bool unbatched)
+{
+    hipError_t st;
+    const int32_t *items = (const int32_t *)e->items.p;
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    if (e->timing) {
+        if (e->ev_free.empty()) {
+            hipEvent_t a, b;
+            if ((st = hipEventCreate(&a)) != hipSuccess) return st;
+            if ((st = hipEventCreate(&b)) != hipSuccess) return st;
+            e->ev_free.push_back({a, b});
+        }
+        ev = e->ev_free.back();
+        e->ev_free.pop_back();
+        e->ev_used.push_back(ev);
+        if ((st = hipEventRecord(ev.first, e->stream)) != hipSuccess) return st;
+    }
+    if (unbatched) {
+        for (int s = 0; s < e->S; ++s)
+            if ((st = launch_sweep(e, K, items + 2 * s, 2)) != hipSuccess) return st;
+    } else {
+        if ((st = launch_sweep(e, K, items, 2 * e->S)) != hipSuccess) return st;
+    }
+    if (e->timing && (st = hipEventRecord(ev.second, e->stream)) != hipSuccess) return st;
+    const int64_t nmeas = measurements_upto(e->sweep + K, e->m, e->mstart) - measurements_upto(e->sweep, e->m, e->mstart);
+    if (nmeas > 0 || e->plan.use_graph) {
+        MeasureArgs M = measure_args(e, K, 0);
+        hipLaunchKernelGGL(measure_kernel, dim3((unsigned)e->total_slots), dim3(256), 0, e->stream, M);
+        if ((st = hipGetLastError()) != hipSuccess) return st;
+    }
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, e->stream, (int64_t *)e->state.p, (int64_t)K);
+    return hipGetLastError();
+}
+
+ea_status run_sweeps(ea_ensemble *e, int64_t n, bool unbatched)
+{
+    if (n < 0) return fail(EA_EINVAL, "n_sweeps must be >= 0");
+    if (e->sweep + n > ((int64_t)1 << 31) - 1)
+        return fail(EA_EINVAL, "sweep counter would exceed 2^31 - 1 (Philox address word 1)");
+    while (n > 0) {
+        const int K = (int)std::min<int64_t>(n, e->plan.chunk);
+        ea_status st = ensure_frames(e, K);
+        if (st) return st;
+        const bool graph = e->plan.use_graph && !e->timing && !unbatched;
+        if (graph) {
+            auto it = e->graphs.find(K);
+            if (it == e->graphs.end()) {
+                hipGraph_t g;
+                HIP_TRY(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+                hipError_t le = enqueue_chunk(e, K, false);
+                hipError_t ce = hipStreamEndCapture(e->stream, &g);
+                if (le != hipSuccess) {
+                    e->dead = true;
+                    return fail(EA_EDEVICE, "launch during capture failed: %s", hipGetErrorString(le));
+                }
+                HIP_TRY(e, ce);
+                hipGraphExec_t ex;
+                HIP_TRY(e, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+                e->graph_defs[K] = g;
+                it = e->graphs.emplace(K, ex).first;
+            }
+            HIP_TRY(e, hipGraphLaunch(it->second, e->stream));
+        } else {
+            hipError_t le = enqueue_chunk(e, K, unbatched);
+            if (le != hipSuccess) {
+                e->dead = true;
+                return fail(EA_EDEVICE, "kernel launch failed: %s", hipGetErrorString(le));
+            }
+        }
+        e->sweep += K;
+        n -= K;
+    }
+    return EA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ea_last_error(void) { return g_err.c_str(); }
+
+ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **out)
+{
+    if (!out) return fail(EA_EINVAL, "out is NULL");
+    *out = nullptr;
+    ea_status st = validate(d);
+    if (st) return st;
+    ea_ensemble *e = new (std::nothrow) ea_ensemble();
+    if (!e) return fail(EA_ENOMEM, "host allocation failed");
+    e->S = d->n_samples;
+    e->jkind = d->jkind;
+    e->seed = d->seed;
+    e->m = d->measure_every;
+    e->mstart = d->measure_start;
+    e->plan.chunk = 100;
+    e->plan.threads = 1024;
+    e->plan.use_graph = 1;
+    if (hipGetDevice(&e->device) != hipSuccess) {
+        delete e;
+        return fail(EA_EDEVICE, "no HIP device");
+    }
+    const size_t lds_max = max_lds_bytes();
+    int64_t soff = 0, joff = 0;
+    int32_t toff = 0;
+    size_t lds_need = 0;
+    for (int s = 0; s < e->S; ++s) {
+        SampleHost h{};
+        h.L = d->L[s];
+        h.nT = d->n_temps[s];
+        h.N = h.L * h.L * h.L;
+        h.id = d->sample_id ? d->sample_id[s] : (uint32_t)s;
+        h.h = d->h[s];
+        h.spin_off = soff;
+        h.J_off = joff;
+        h.slot_off = toff;
+        const size_t need = lds_offsets(h.L, h.nT, e->jkind).total;
+        if (h.L > LDS_MAX_L || need > lds_max) {
+            destroy_all(e);
+            return fail(EA_EUNSUPPORTED, "sample %d: L=%d with %d temperatures needs %zu B of LDS (limit %zu, L <= %d)",
+                        s, h.L, h.nT, need, lds_max, LDS_MAX_L);
+        }
+        lds_need = std::max(lds_need, need);
+        soff += 2 * (int64_t)h.nT * h.N;
+        joff += 3 * (int64_t)h.N;
+        toff += h.nT;
+        e->smp.push_back(h);
+    }
+    e->total_slots = toff;
+    e->spin_bytes = soff;
+    e->J_elems = joff;
+    e->lds_needed = lds_need;
+
+    if (hip_stream) {
+        e->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess) {
+            destroy_all(e);
+            return fail(EA_EDEVICE, "stream creation failed");
+        }
+        e->own_stream = true;
+    }
+    hipError_t fa = hipFuncSetAttribute((const void *)lds_sweep_kernel<0>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+    if (fa == hipSuccess)
+        fa = hipFuncSetAttribute((const void *)lds_sweep_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds_max);
+    (void)fa;  // not every runtime needs (or accepts) the opt-in; launches report real failures
+
+    // host-side layouts
+    const int S = e->S;
+    std::vector<SampleDev> sd(S);
+    std::vector<int32_t> items(2 * S), slot_sample(e->total_slots);
+    std::vector<int8_t> spins(e->spin_bytes);
+    const size_t jsz = e->jkind == EA_J_GAUSS_F32 ? 4 : 1;
+    std::vector<char> Jsub((size_t)e->J_elems * jsz);
+    std::vector<double> beta(e->total_slots);
+    std::vector<float> beta32(e->total_slots);
+    std::vector<uint32_t> lut(e->total_slots * 14);
+    std::vector<int32_t> was(2 * e->total_slots);
+    for (int s = 0; s < S; ++s) {
+        const SampleHost &h = e->smp[s];
+        const int N = h.N, HALF = N / 2;
+        sd[s] = SampleDev{h.L, h.nT, h.id, h.h, h.spin_off, h.J_off, h.slot_off, 0};
+        items[2 * s] = 2 * s;
+        items[2 * s + 1] = 2 * s + 1;
+        for (int t = 0; t < h.nT; ++t) {
+            slot_sample[h.slot_off + t] = s;
+            beta[h.slot_off + t] = d->beta[h.slot_off + t];
+            beta32[h.slot_off + t] = (float)d->beta[h.slot_off + t];
+            was[2 * h.slot_off + t] = t;
+            was[2 * h.slot_off + h.nT + t] = t;
+        }
+        for (int i = 0; i < N; ++i) {
+            const int p = parity(h.L, i), hh = i >> 1;
+            for (int dd = 0; dd < 3; ++dd)
+                std::memcpy(&Jsub[((size_t)h.J_off + (size_t)p * 3 * HALF + dd * HALF + hh) * jsz],
+                            (const char *)d->J + ((size_t)h.J_off + (size_t)dd * N + i) * jsz, jsz);
+        }
+        for (int rw = 0; rw < 2 * h.nT; ++rw) {
+            const int8_t *src = d->spins0 + h.spin_off + (size_t)rw * N;
+            int8_t *dst = spins.data() + h.spin_off + (size_t)rw * N;
+            for (int i = 0; i < N; ++i) dst[parity(h.L, i) * HALF + (i >> 1)] = src[i];
+        }
+        if (e->jkind == EA_J_PM1_I8) {
+            for (int t = 0; t < h.nT; ++t)
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 7; ++b) {
+                        const double si = a ? 1.0 : -1.0, SJ = 2.0 * b - 6.0;
+                        const double dE = 2.0 * si * (SJ + (double)h.h);
+                        uint32_t v = 0xFFFFFFFFu;
+                        if (dE > 0.0) {
+                            const double pr = std::ldexp(std::exp(-d->beta[h.slot_off + t] * dE), 32);
+                            v = pr >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(pr);
+                        }
+                        lut[((size_t)(h.slot_off + t) * 2 + a) * 7 + b] = v;
+                    }
+        }
+    }
+    std::vector<double> costab((MAX_L + 1) * MAX_L, 0.0), sintab((MAX_L + 1) * MAX_L, 0.0);
+    for (int L = 1; L <= MAX_L; ++L)
+        for (int c = 0; c < L; ++c) {
+            const double th = (2.0 * M_PI * (double)c) / (double)L;
+            costab[L * MAX_L + c] = std::cos(th);
+            sintab[L * MAX_L + c] = std::sin(th);
+        }
+
+    const int64_t TS = e->total_slots;
+#define ALLOC(buf, bytes)                          \
+    do {                                           \
+        ea_status a_ = dalloc(e, e->buf, (bytes)); \
+        if (a_) {                                  \
+            destroy_all(e);                        \
+            return a_;                             \
+        }                                          \
+    } while (0)
+    ALLOC(samples, sizeof(SampleDev) * S);
+    ALLOC(items, sizeof(int32_t) * 2 * S);
+    ALLOC(spins, (size_t)e->spin_bytes);
+    ALLOC(J, Jsub.size());
+    ALLOC(beta, sizeof(double) * TS);
+    ALLOC(beta32, sizeof(float) * TS);
+    ALLOC(lut, sizeof(uint32_t) * 14 * TS);
+    ALLOC(was, sizeof(int32_t) * 2 * TS);
+    ALLOC(EJ, sizeof(int64_t) * 2 * TS);
+    ALLOC(M, sizeof(int32_t) * 2 * TS);
+    ALLOC(flips, sizeof(int64_t) * 2 * TS);
+    ALLOC(swaps, sizeof(int64_t) * 2 * TS);
+    ALLOC(acc, sizeof(double) * NACC * TS);
+    ALLOC(state, 64);
+    ALLOC(slot_sample, sizeof(int32_t) * TS);
+    ALLOC(costab, sizeof(double) * costab.size());
+    ALLOC(sintab, sizeof(double) * sintab.size());
+    ALLOC(finout, sizeof(double) * MAX_T * EA_NOBS);
+#undef ALLOC
+    {
+        ea_status fs = ensure_frames(e, e->plan.chunk);
+        if (fs) {
+            destroy_all(e);
+            return fs;
+        }
+    }
+#define H2D(buf, src, bytes)                                                                          \
+    do {                                                                                              \
+        hipError_t c_ = hipMemcpyAsync(e->buf.p, (src), (bytes), hipMemcpyHostToDevice, e->stream); \
+        if (c_ != hipSuccess) {                                                                       \
+            destroy_all(e);                                                                           \
+            return fail(EA_EDEVICE, "copy to device failed: %s", hipGetErrorString(c_));              \
+        }                                                                                             \
+    } while (0)
+    H2D(samples, sd.data(), sizeof(SampleDev) * S);
+    H2D(items, items.data(), sizeof(int32_t) * 2 * S);
+    H2D(spins, spins.data(), (size_t)e->spin_bytes);
+    H2D(J, Jsub.data(), Jsub.size());
+    H2D(beta, beta.data(), sizeof(double) * TS);
+    H2D(beta32, beta32.data(), sizeof(float) * TS);
+    H2D(lut, lut.data(), sizeof(uint32_t) * 14 * TS);
+    H2D(was, was.data(), sizeof(int32_t) * 2 * TS);
+    H2D(slot_sample, slot_sample.data(), sizeof(int32_t) * TS);
+    H2D(costab, costab.data(), sizeof(double) * costab.size());
+    H2D(sintab, sintab.data(), sizeof(double) * sintab.size());
+#undef H2D
+    if (hipMemsetAsync(e->flips.p, 0, e->flips.bytes, e->stream) != hipSuccess ||
+        hipMemsetAsync(e->swaps.p, 0, e->swaps.bytes, e->stream) != hipSuccess ||
+        hipMemsetAsync(e->acc.p, 0, e->acc.bytes, e->stream) != hipSuccess ||
+        hipMemsetAsync(e->state.p, 0, e->state.bytes, e->stream) != hipSuccess) {
+        destroy_all(e);
+        return fail(EA_EDEVICE, "memset failed");
+    }
+    // initial energies from scratch on the device
+    if (e->jkind == EA_J_GAUSS_F32)
+        hipLaunchKernelGGL(energy_kernel<0>, dim3(2 * S), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
+                           (const int32_t *)e->items.p, (const int8_t *)e->spins.p, e->J.p, (int64_t *)e->EJ.p,
+                           (int32_t *)e->M.p);
+    else
+        hipLaunchKernelGGL(energy_kernel<1>, dim3(2 * S), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
+                           (const int32_t *)e->items.p, (const int8_t *)e->spins.p, e->J.p, (int64_t *)e->EJ.p,
+                           (int32_t *)e->M.p);
+    hipError_t le = hipGetLastError();
+    if (le == hipSuccess) le = hipStreamSynchronize(e->stream);
+    if (le != hipSuccess) {
+        destroy_all(e);
+        return fail(EA_EDEVICE, "initialisation failed: %s", hipGetErrorString(le));
+    }
+    *out = e;
+    return EA_OK;
+}
+
+ea_status ea_sweep_pt(ea_ensemble *e, int64_t n)
+{
+    if (!usable(e)) return EA_ESTATE;
+    return run_sweeps(e, n, false);
+}
+
+ea_status ea_sweep_pt_unbatched(ea_ensemble *e, int64_t n)
+{
+    if (!usable(e)) return EA_ESTATE;
+    return run_sweeps(e, n, true);
+}
+
+ea_status ea_measure(ea_ensemble *e, int32_t flags, double *acc, int64_t *flips, int64_t *swaps)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (flags & ~EA_MEASURE_NOW) return fail(EA_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & EA_MEASURE_NOW) {
+        ea_status st = ensure_frames(e, e->plan.chunk);
+        if (st) return st;
+        hipLaunchKernelGGL(snapshot_kernel, dim3(2 * e->S), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
+                           (const int32_t *)e->items.p, (const int8_t *)e->spins.p, (const int32_t *)e->was.p,
+                           (const int64_t *)e->EJ.p, (const int32_t *)e->M.p, e->jkind, (int8_t *)e->frames.p,
+                           (double *)e->frameE.p);
+        HIP_TRY(e, hipGetLastError());
+        MeasureArgs M = measure_args(e, 0, 1);
+        hipLaunchKernelGGL(measure_kernel, dim3((unsigned)e->total_slots), dim3(256), 0, e->stream, M);
+        HIP_TRY(e, hipGetLastError());
+    }
+    if (acc) HIP_TRY(e, hipMemcpyAsync(acc, e->acc.p, e->acc.bytes, hipMemcpyDeviceToHost, e->stream));
+    if (flips) HIP_TRY(e, hipMemcpyAsync(flips, e->flips.p, e->flips.bytes, hipMemcpyDeviceToHost, e->stream));
+    if (swaps) HIP_TRY(e, hipMemcpyAsync(swaps, e->swaps.p, e->swaps.bytes, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    return EA_OK;
+}
+
+ea_status ea_read_state(ea_ensemble *e, int8_t *spins_out, int32_t *was_out, double *E_out, int64_t *sweep)
+{
+    if (!usable(e)) return EA_ESTATE;
+    const int64_t TS = e->total_slots;
+    std::vector<int8_t> sp(spins_out ? e->spin_bytes : 0);
+    std::vector<int32_t> was(2 * TS), M(2 * TS);
+    std::vector<int64_t> EJ(2 * TS);
+    if (spins_out) HIP_TRY(e, hipMemcpyAsync(sp.data(), e->spins.p, e->spin_bytes, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(was.data(), e->was.p, e->was.bytes, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(EJ.data(), e->EJ.p, e->EJ.bytes, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(M.data(), e->M.p, e->M.bytes, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    const double unit = e->jkind == EA_J_GAUSS_F32 ? 0x1p-18 : 1.0;
+    for (int s = 0; s < e->S; ++s) {
+        const SampleHost &h = e->smp[s];
+        const int N = h.N, HALF = N / 2;
+        for (int r = 0; r < 2; ++r)
+            for (int t = 0; t < h.nT; ++t) {
+                const size_t gi = 2 * (size_t)h.slot_off + (size_t)r * h.nT;
+                const int w = was[gi + t];
+                if (was_out) was_out[gi + t] = w;
+                if (E_out) E_out[gi + t] = (double)EJ[gi + w] * unit - (double)h.h * (double)M[gi + w];
+                if (spins_out) {
+                    const int8_t *src = sp.data() + h.spin_off + ((size_t)r * h.nT + w) * N;
+                    int8_t *dst = spins_out + h.spin_off + ((size_t)r * h.nT + t) * N;
+                    for (int i = 0; i < N; ++i) dst[i] = src[parity(h.L, i) * HALF + (i >> 1)];
+                }
+            }
+    }
+    if (sweep) *sweep = e->sweep;
+    return EA_OK;
+}
+
+ea_status ea_write_state(ea_ensemble *e, const int8_t *spins_in, int64_t sweep)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (!spins_in) return fail(EA_EINVAL, "spins is NULL");
+    if (sweep < 0 || sweep > ((int64_t)1 << 31) - 1) return fail(EA_EINVAL, "sweep out of range");
+    std::vector<int8_t> sp(e->spin_bytes);
+    std::vector<int32_t> was(2 * e->total_slots);
+    for (int s = 0; s < e->S; ++s) {
+        const SampleHost &h = e->smp[s];
+        const int N = h.N, HALF = N / 2;
+        for (int rw = 0; rw < 2 * h.nT; ++rw) {
+            const int8_t *src = spins_in + h.spin_off + (size_t)rw * N;
+            int8_t *dst = sp.data() + h.spin_off + (size_t)rw * N;
+            for (int i = 0; i < N; ++i) {
+                if (src[i] != 1 && src[i] != -1) return fail(EA_EINVAL, "sample %d: spin not +-1", s);
+                dst[parity(h.L, i) * HALF + (i >> 1)] = src[i];
+            }
+        }
+        for (int r = 0; r < 2; ++r)
+            for (int t = 0; t < h.nT; ++t) was[2 * (size_t)h.slot_off + r * h.nT + t] = t;
+    }
+    HIP_TRY(e, hipMemcpyAsync(e->spins.p, sp.data(), e->spin_bytes, hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(e->was.p, was.data(), e->was.bytes, hipMemcpyHostToDevice, e->stream));
+    int64_t sw = sweep;
+    HIP_TRY(e, hipMemcpyAsync(e->state.p, &sw, sizeof sw, hipMemcpyHostToDevice, e->stream));
+    if (e->jkind == EA_J_GAUSS_F32)
+        hipLaunchKernelGGL(energy_kernel<0>, dim3(2 * e->S), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
+                           (const int32_t *)e->items.p, (const int8_t *)e->spins.p, e->J.p, (int64_t *)e->EJ.p,
+                           (int32_t *)e->M.p);
+    else
+        hipLaunchKernelGGL(energy_kernel<1>, dim3(2 * e->S), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
+                           (const int32_t *)e->items.p, (const int8_t *)e->spins.p, e->J.p, (int64_t *)e->EJ.p,
+                           (int32_t *)e->M.p);
+    HIP_TRY(e, hipGetLastError());
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    e->sweep = sweep;
+    return EA_OK;
+}
+
+ea_status ea_load_accumulators(ea_ensemble *e, const double *acc, const int64_t *flips, const int64_t *swaps)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (acc) HIP_TRY(e, hipMemcpyAsync(e->acc.p, acc, e->acc.bytes, hipMemcpyHostToDevice, e->stream));
+    if (flips) HIP_TRY(e, hipMemcpyAsync(e->flips.p, flips, e->flips.bytes, hipMemcpyHostToDevice, e->stream));
+    if (swaps) HIP_TRY(e, hipMemcpyAsync(e->swaps.p, swaps, e->swaps.bytes, hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    return EA_OK;
+}
+
+ea_status ea_reset_accumulators(ea_ensemble *e)
+{
+    if (!usable(e)) return EA_ESTATE;
+    HIP_TRY(e, hipMemsetAsync(e->acc.p, 0, e->acc.bytes, e->stream));
+    HIP_TRY(e, hipMemsetAsync(e->flips.p, 0, e->flips.bytes, e->stream));
+    HIP_TRY(e, hipMemsetAsync(e->swaps.p, 0, e->swaps.bytes, e->stream));
+    return EA_OK;
+}
+
+ea_status ea_check_energies(ea_ensemble *e, int64_t *mismatches)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (!mismatches) return fail(EA_EINVAL, "mismatches is NULL");
+    const int64_t TS = e->total_slots;
+    if (!e->scratchE.p) {
+        ea_status st = dalloc(e, e->scratchE, sizeof(int64_t) * 2 * TS);
+        if (st) return st;
+        st = dalloc(e, e->scratchM, sizeof(int32_t) * 2 * TS);
+        if (st) return st;
+    }
+    if (e->jkind == EA_J_GAUSS_F32)
+        hipLaunchKernelGGL(energy_kernel<0>, dim3(2 * e->S), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
+                           (const int32_t *)e->items.p, (const int8_t *)e->spins.p, e->J.p,
+                           (int64_t *)e->scratchE.p, (int32_t *)e->scratchM.p);
+    else
+        hipLaunchKernelGGL(energy_kernel<1>, dim3(2 * e->S), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
+                           (const int32_t *)e->items.p, (const int8_t *)e->spins.p, e->J.p,
+                           (int64_t *)e->scratchE.p, (int32_t *)e->scratchM.p);
+    HIP_TRY(e, hipGetLastError());
+    std::vector<int64_t> a(2 * TS), b(2 * TS);
+    std::vector<int32_t> ma(2 * TS), mb(2 * TS);
+    HIP_TRY(e, hipMemcpyAsync(a.data(), e->EJ.p, e->EJ.bytes, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(b.data(), e->scratchE.p, e->EJ.bytes, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(ma.data(), e->M.p, e->M.bytes, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(mb.data(), e->scratchM.p, e->M.bytes, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    int64_t bad = 0;
+    for (int64_t i = 0; i < 2 * TS; ++i) bad += (a[i] != b[i]) || (ma[i] != mb[i]);
+    *mismatches = bad;
+    return EA_OK;
+}
+
+ea_status ea_finalize(ea_ensemble *e, int32_t L, int32_t nT, double *out)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (!out) return fail(EA_EINVAL, "out is NULL");
+    if (nT < 1 || nT > MAX_T) return fail(EA_EINVAL, "n_temps out of range");
+    bool any = false;
+    for (const auto &h : e->smp) any |= (h.L == L && h.nT == nT);
+    if (!any) return fail(EA_EINVAL, "no sample with L=%d and %d temperatures", L, nT);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, e->stream, (const SampleDev *)e->samples.p, e->S, L, nT,
+                       (const double *)e->acc.p, (double *)e->finout.p);
+    HIP_TRY(e, hipGetLastError());
+    HIP_TRY(e, hipMemcpyAsync(out, e->finout.p, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    return EA_OK;
+}
+
+ea_status ea_set_plan(ea_ensemble *e, const ea_plan *p)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (!p) return fail(EA_EINVAL, "plan is NULL");
+    if (p->chunk < 1 || p->chunk > 100000) return fail(EA_EINVAL, "chunk must be in [1, 100000]");
+    if (p->threads != 256 && p->threads != 512 && p->threads != 1024)
+        return fail(EA_EINVAL, "threads must be 256, 512 or 1024");
+    for (const auto &h : e->smp)
+        if ((int64_t)p->chunk * h.N >= ((int64_t)1 << 31))
+            return fail(EA_EINVAL, "chunk too long for the per-chunk flip counters");
+    e->plan = *p;
+    return EA_OK;
+}
+
+ea_status ea_get_plan(const ea_ensemble *e, ea_plan *p)
+{
+    if (!e || !p) return fail(EA_EINVAL, "null argument");
+    *p = e->plan;
+    return EA_OK;
+}
+
+ea_status ea_set_timing(ea_ensemble *e, int32_t enable)
+{
+    if (!usable(e)) return EA_ESTATE;
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    for (auto &p : e->ev_used) e->ev_free.push_back(p);
+    e->ev_used.clear();
+    e->timing = enable != 0;
+    e->timed_ms = 0.0;
+    e->timed_launches = 0;
+    return EA_OK;
+}
+
+ea_status ea_kernel_time(ea_ensemble *e, double *ms_total, int64_t *launches)
+{
+    if (!usable(e)) return EA_ESTATE;
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    for (auto &p : e->ev_used) {
+        float ms = 0.f;
+        HIP_TRY(e, hipEventElapsedTime(&ms, p.first, p.second));
+        e->timed_ms += ms;
+        e->timed_launches += 1;
+        e->ev_free.push_back(p);
+    }
+    e->ev_used.clear();
+    if (ms_total) *ms_total = e->timed_ms;
+    if (launches) *launches = e->timed_launches;
+    return EA_OK;
+}
+
+ea_status ea_autotune(ea_ensemble *e, int32_t trial_sweeps)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (trial_sweeps < 1) return fail(EA_EINVAL, "trial_sweeps must be >= 1");
+    // back up the mutable state, time each candidate, restore
+    DevBuf *mut[] = {&e->spins, &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->state};
+    std::vector<DevBuf> bak(8);
+    for (int i = 0; i < 8; ++i) {
+        ea_status st = dalloc(e, bak[i], mut[i]->bytes);
+        if (st) {
+            for (auto &b : bak) dfree(b);
+            return st;
+        }
+        HIP_TRY(e, hipMemcpyAsync(bak[i].p, mut[i]->p, mut[i]->bytes, hipMemcpyDeviceToDevice, e->stream));
+    }
+    const int64_t sweep0 = e->sweep;
+    const ea_plan orig = e->plan;
+    const bool timing = e->timing;
+    e->timing = false;
+    ea_plan best = orig;
+    double best_ms = 1e300;
+    const int cand[3] = {256, 512, 1024};
+    hipEvent_t a, b;
+    HIP_TRY(e, hipEventCreate(&a));
+    HIP_TRY(e, hipEventCreate(&b));
+    ea_status result = EA_OK;
+    for (int c = 0; c < 3 && result == EA_OK; ++c) {
+        ea_plan p = orig;
+        p.threads = cand[c];
+        p.use_graph = 0;
+        p.chunk = trial_sweeps;
+        e->plan = p;
+        HIP_TRY(e, hipEventRecord(a, e->stream));
+        result = run_sweeps(e, trial_sweeps, false);
+        HIP_TRY(e, hipEventRecord(b, e->stream));
+        HIP_TRY(e, hipEventSynchronize(b));
+        float ms = 0.f;
+        HIP_TRY(e, hipEventElapsedTime(&ms, a, b));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = orig;
+            best.threads = cand[c];
+        }
+        for (int i = 0; i < 8; ++i)
+            HIP_TRY(e, hipMemcpyAsync(mut[i]->p, bak[i].p, mut[i]->bytes, hipMemcpyDeviceToDevice, e->stream));
+        e->sweep = sweep0;
+    }
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    for (auto &bb : bak) {
+        e->device_bytes -= (int64_t)bb.bytes;
+        dfree(bb);
+    }
+    e->timing = timing;
+    e->plan = best;
+    return result;
+}
+
+ea_status ea_synchronize(ea_ensemble *e)
+{
+    if (!usable(e)) return EA_ESTATE;
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    return EA_OK;
+}
+
+ea_status ea_query(const ea_ensemble *e, int32_t *n_samples, int64_t *total_slots, int64_t *device_bytes)
+{
+    if (!e) return fail(EA_EINVAL, "null ensemble");
+    if (n_samples) *n_samples = e->S;
+    if (total_slots) *total_slots = e->total_slots;
+    if (device_bytes) *device_bytes = e->device_bytes;
+    return EA_OK;
+}
+
+void ea_destroy(ea_ensemble *e) { destroy_all(e); }
+
+}  // extern "C"

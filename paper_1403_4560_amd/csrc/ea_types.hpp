@@ -1,0 +1,126 @@
+// ea_types.hpp -- layouts shared by the host library and the gfx950 kernels.
+//
+// Device memory of an ensemble (all offsets precomputed on the host):
+//   spins   int8   per sample [2 chains][n_T walkers][2 parities][N/2]
+//                  (walker order; a walker's bytes never move, exchanges
+//                  permute the walker <-> slot maps instead)
+//   Jsub    float  per sample [2 parities][3 directions][N/2] (Gaussian), or
+//           int8   the same shape for +-1 couplings.  Jsub[p][d][h] is the
+//                  bond from the parity-p site with sublattice index h to its
+//                  +d neighbour.
+//   per (sample, chain, slot or walker), index 2*slot_off + r*n_T + t:
+//           walker_at_slot int32, EJ int64 (coupling energy in units of
+//           2^-18 for Gaussian couplings, 1 for +-1), M int32 (magnetisation,
+//           per walker), flips int64 and swaps int64 (per slot / pair)
+//   per (sample, slot), index slot_off + t: beta float64, beta32 float32,
+//           acc float64[36], lut uint32[2][7] (+-1 couplings)
+//   frames  int8   snapshot frames of both chains in slot order, one frame per
+//                  measurement in a chunk: frame f, sample s at
+//                  f*frame_bytes + spin_off[s], layout [2][n_T][2][N/2]
+//   frameE  float64 [frame][2*total_slots] energies of the snapshotted walkers
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ea {
+
+constexpr int NACC = 36;
+constexpr int NPLANE = 9;
+constexpr int MAX_T = 64;     // temperature slots per sample
+constexpr int MAX_L = 64;
+constexpr int LDS_MAX_L = 16; // largest lattice of the LDS-resident tier
+
+struct SampleDev {
+    int32_t L;
+    int32_t n_T;
+    uint32_t sample_id;
+    float h32;
+    int64_t spin_off;   // bytes into spins (and into each frame)
+    int64_t J_off;      // elements into Jsub
+    int32_t slot_off;   // sum of n_T over earlier samples
+    int32_t tier;       // 0 = LDS-resident, 1 = HBM-resident
+};
+
+struct SweepArgs {
+    const SampleDev *samples;
+    const int32_t *items;       // (sample << 1) | chain, one per workgroup
+    int32_t n_items;
+    int32_t K;                  // sweeps in this launch
+    int8_t *spins;
+    const void *J;
+    const double *beta;
+    const float *beta32;
+    const uint32_t *lut;
+    int32_t *was;
+    int64_t *EJ;
+    int32_t *M;
+    int64_t *flips;
+    int64_t *swaps;
+    int8_t *frames;
+    double *frameE;
+    int64_t frame_bytes;
+    int64_t total_slots;
+    const int64_t *state;       // [0] sweeps completed before this launch
+    uint32_t key0, key1;
+    int32_t measure_every;
+    int32_t pad;
+    int64_t measure_start;
+};
+
+struct MeasureArgs {
+    const SampleDev *samples;
+    const int32_t *slot_sample;  // global slot -> sample
+    const int8_t *frames;
+    const double *frameE;
+    int64_t frame_bytes;
+    int64_t total_slots;
+    double *acc;
+    const double *costab;        // [MAX_L + 1][MAX_L]: cos(2 pi c / L)
+    const double *sintab;
+    const int64_t *state;
+    int32_t K;                   // chunk length (frames derived from state)
+    int32_t explicit_frames;     // > 0: measure this many frames regardless
+    int32_t measure_every;
+    int32_t pad;
+    int64_t measure_start;
+};
+
+// Number of measurement sweeps among completed-sweep counts 1..x.
+__host__ __device__ inline int64_t measurements_upto(int64_t x, int32_t m, int64_t start)
+{
+    if (m <= 0 || x <= start) return 0;
+    return (x - start) / m;
+}
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS layout of one LDS-tier work item (bytes).  Shared with the host, which
+// sizes the dynamic LDS of a launch with lds_total().
+struct LdsOff {
+    size_t spins, J, was, sow, M, dM, fl, sw, EJ, dEJ, lut, b32, b64, total;
+};
+
+__host__ __device__ inline LdsOff lds_offsets(int L, int nT, int jkind)
+{
+    const size_t N = (size_t)L * L * L;
+    const size_t T4 = (size_t)((nT + 3) & ~3);
+    LdsOff o;
+    o.spins = 0;
+    o.J = align16((size_t)nT * N);
+    o.was = o.J + align16(3 * N * (jkind == 0 ? 4 : 1));
+    o.sow = o.was + 4 * T4;
+    o.M = o.sow + 4 * T4;
+    o.dM = o.M + 4 * T4;
+    o.fl = o.dM + 4 * T4;
+    o.sw = o.fl + 4 * T4;
+    o.EJ = align16(o.sw + 4 * T4);
+    o.dEJ = o.EJ + 8 * T4;
+    o.lut = o.dEJ + 8 * T4;
+    o.b32 = o.lut + (jkind == 1 ? 4 * 14 * T4 : 0);
+    o.b64 = align16(o.b32 + 4 * T4);
+    o.total = align16(o.b64 + 8 * T4);
+    return o;
+}
+
+}  // namespace ea

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer and byte results (spins, walker maps, flip and exchange counters) and
+the binary64 energies and accumulators must be bit-identical: both sides run
+the same numeric contract (see the oracle header), and every floating-point
+sum on the GPU path is either exact or taken in the oracle's order.  Finalized
+observables (a different summation order over samples) must agree to 1e-12
+relative, or to the bound the conditioning of eq. 3 allows (see the test).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ea_oracle as O
+from paper_1403_4560_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+def gpu_run(work, sweeps, stream=None, plan=None, splits=None, unbatched=False):
+    from paper_1403_4560_amd import binding
+    with binding.Ensemble(work, stream=stream) as ens:
+        if plan:
+            ens.set_plan(**plan)
+        parts = splits or [sweeps]
+        assert sum(parts) == sweeps
+        for k in parts:
+            (ens.sweep_pt_unbatched if unbatched else ens.sweep_pt)(k)
+        st = ens.read_state()
+        ms = ens.measure()
+        bad = ens.check_energies()
+    return st, ms, bad
+
+
+def assert_same(work, st, ms, ref, samples=None):
+    samples = range(work.n_samples) if samples is None else samples
+    for k, s in enumerate(samples):
+        o = ref.states[k]
+        assert st["sweep"] == int(o.sweep[0])
+        assert np.array_equal(st["walker_at_slot"][s], o.walker_at_slot), ("walker_at_slot", s)
+        assert np.array_equal(st["spins"][s], o.spins_slot_order()), ("spins", s)
+        assert np.array_equal(st["E"][s], o.energies_slot_order()), ("E", s)
+        assert np.array_equal(ms["flips"][s], o.flips), ("flips", s)
+        assert np.array_equal(ms["swaps"][s], o.swaps), ("swaps", s)
+        assert np.array_equal(ms["acc"][s], o.acc), ("acc", s)
+
+
+def check(work, sweeps, **kw):
+    print("case:", work.name, "S=%d" % work.n_samples, "sweeps=%d" % sweeps, kw, flush=True)
+    st, ms, bad = gpu_run(work, sweeps, **kw)
+    ref = O.OracleEnsemble(work).run(sweeps)
+    assert bad == 0
+    assert_same(work, st, ms, ref)
+    return st, ms, ref
+
+
+def test_L4_workload_in_full(torch_cuda):
+    # 16 samples, 8 temperatures, 5000 sweeps, measurements every 10 from 2500
+    work = W.config_workload("L4_gauss")
+    st, ms, ref = check(work, work.sweeps, stream=torch_cuda.cuda.current_stream().cuda_stream)
+    assert ms["acc"][0][0, 0] == 250.0
+
+
+def test_L8_subset_several_tiles(torch_cuda):
+    work = W.config_workload("L8_gauss", samples=[0, 5, 1023], measure_start=100)
+    check(work, 400, plan=dict(threads=256))
+
+
+def test_mixed_sizes_and_fields(torch_cuda):
+    work = W.config_workload("mixed_L6_12", samples=range(12), measure_start=50)
+    check(work, 160)
+
+
+def test_L16_subset(torch_cuda):
+    work = W.config_workload("L16_gauss", samples=[0, 2047], measure_start=0)
+    check(work, 40)
+
+
+def test_pm1_couplings_lds_tier(torch_cuda):
+    work = W.make_workload([8, 4, 6], 6, (0.5, 2.0), 0.4, jkind=W.J_PM1, measure_every=5,
+                           measure_start=20, name="pm1")
+    check(work, 150)
+
+
+def test_degenerate_sizes(torch_cuda):
+    # L = 2 (every neighbour pair joined by two bonds), one temperature (no
+    # exchange), an odd number of temperatures, L = 14
+    work = W.make_workload([2, 2, 4, 14], [1, 5, 3, 2], (0.5, 2.0), [0.3, 0.0, 0.1, 0.2],
+                           measure_every=3, measure_start=5, name="degenerate")
+    check(work, 50)
+
+
+def test_never_measure(torch_cuda):
+    work = W.make_workload([4, 6], 4, (0.5, 2.0), 0.3, measure_every=0, name="m0")
+    st, ms, ref = check(work, 30)
+    assert all((a == 0).all() for a in ms["acc"])
+
+
+@pytest.mark.parametrize("plan", [dict(threads=256, chunk=1, use_graph=0),
+                                  dict(threads=512, chunk=7, use_graph=1),
+                                  dict(threads=1024, chunk=100, use_graph=0),
+                                  dict(threads=1024, chunk=13, use_graph=1)])
+def test_plan_invariance(torch_cuda, plan):
+    work = W.config_workload("mixed_L6_12", samples=[0, 1, 2, 3, 16, 17], measure_start=10)
+    check(work, 45, plan=plan)
+
+
+def test_chunking_invariance(torch_cuda):
+    work = W.config_workload("L8_gauss", samples=[3, 4], measure_start=30)
+    check(work, 100, splits=[37, 1, 62], plan=dict(chunk=16))
+
+
+def test_unbatched_equals_oracle(torch_cuda):
+    work = W.config_workload("L8_gauss", samples=[7, 8, 9], measure_start=20)
+    check(work, 60, unbatched=True)
+
+
+def test_batch_invariance(torch_cuda):
+    work = W.config_workload("mixed_L6_12", samples=range(8), measure_start=0)
+    st_all, ms_all, _ = gpu_run(work, 30)
+    one = work.subset([5])
+    st_one, ms_one, _ = gpu_run(one, 30)
+    assert np.array_equal(st_all["spins"][5], st_one["spins"][0])
+    assert np.array_equal(ms_all["acc"][5], ms_one["acc"][0])
+
+
+def test_checkpoint_resume(torch_cuda):
+    from paper_1403_4560_amd import binding
+    work = W.config_workload("L8_gauss", samples=[11, 12], measure_start=10)
+    st_full, ms_full, _ = gpu_run(work, 80)
+    with binding.Ensemble(work) as a:
+        a.sweep_pt(35)
+        st = a.read_state()
+        ms = a.measure()
+    with binding.Ensemble(work) as b:
+        b.write_state(st["spins"], st["sweep"])
+        b.load_accumulators(ms["acc"], ms["flips"], ms["swaps"])
+        b.sweep_pt(45)
+        st2 = b.read_state()
+        ms2 = b.measure()
+    for s in range(2):
+        assert np.array_equal(st2["spins"][s], st_full["spins"][s])
+        assert np.array_equal(st2["E"][s], st_full["E"][s])
+        assert np.array_equal(ms2["acc"][s], ms_full["acc"][s])
+        assert np.array_equal(ms2["swaps"][s], ms_full["swaps"][s])
+
+
+def test_measure_now_matches_oracle(torch_cuda):
+    from paper_1403_4560_amd import binding
+    work = W.make_workload([6, 4], 3, (0.5, 2.0), 0.2, measure_every=0, name="now")
+    with binding.Ensemble(work) as ens:
+        ens.sweep_pt(12)
+        st = ens.read_state()
+        ms = ens.measure(now=True)
+    for s in range(2):
+        L = int(work.L[s])
+        for t in range(int(work.n_temps[s])):
+            acc, _ = O.measure_pair(L, st["spins"][s][0, t], st["spins"][s][1, t],
+                                    st["E"][s][0, t], st["E"][s][1, t])
+            assert np.array_equal(ms["acc"][s][t], acc)
+
+
+def test_finalize_matches_oracle(torch_cuda):
+    from paper_1403_4560_amd import binding
+    work = W.config_workload("L4_gauss", measure_start=200)
+    with binding.Ensemble(work) as ens:
+        ens.sweep_pt(1200)
+        ms = ens.measure()
+        fin = ens.finalize(4, 8)
+    acc = np.stack(ms["acc"])
+    ref = O.observables(acc, 4)
+    assert np.all(fin["n_samples"] == 16)
+    for k_gpu, k_ref in [("q", "q"), ("chi0", "chi0"), ("chi_kmin", "chi_kmin"), ("chi_k2", "chi_k2"),
+                         ("R12", "R12"), ("chi0_over_chikmin", "chi0_over_chikmin"), ("E_a", "E_a"),
+                         ("E_b", "E_b")]:
+        assert np.allclose(fin[k_gpu], ref[k_ref], rtol=1e-12, atol=0), k_gpu
+    # g = (3 - c4/c2^2)/2 loses |3/(2g)| * (cancellation in c4) digits; both
+    # sides expand the same central moments, so 1e-9 relative is generous.
+    assert np.allclose(fin["g"], ref["g"], rtol=1e-9, atol=1e-12)
+    ok = ~np.isnan(ref["xi_L"])
+    assert np.array_equal(ok, ~np.isnan(fin["xi_L"]))
+    assert np.allclose(fin["xi_L"][ok], ref["xi_L"][ok], rtol=1e-10)
+
+
+def test_full_L16_workload_sampled(torch_cuda):
+    """The 2048-sample, 24-temperature L = 16 batch in the benchmark's launch
+    configuration; samples compared one by one against the oracle."""
+    from paper_1403_4560_amd import binding
+    work = W.config_workload("L16_gauss", measure_start=0)
+    sweeps = 20
+    print("case: full L16 batch, 2048 samples, %d sweeps" % sweeps, flush=True)
+    with binding.Ensemble(work) as ens:
+        ens.set_plan(chunk=10)
+        ens.sweep_pt(sweeps)
+        st = ens.read_state()
+        ms = ens.measure()
+        assert ens.check_energies() == 0
+    pick = [0, 777, 2047]
+    ref = O.OracleEnsemble(work.subset(pick)).run(sweeps)
+    assert_same(work, st, ms, ref, samples=pick)
+
+
+def test_invalid_plan_rejected(torch_cuda):
+    from paper_1403_4560_amd import binding
+    work = W.make_workload([4], 2, (0.5, 2.0), 0.3)
+    with binding.Ensemble(work) as ens:
+        with pytest.raises(binding.EAError):
+            ens.set_plan(threads=300)
+        with pytest.raises(binding.EAError):
+            ens.set_plan(chunk=0)
+        with pytest.raises(binding.EAError):
+            ens.sweep_pt(-1)
