@@ -1,0 +1,195 @@
+"""Benchmark: Metropolis + parallel-tempering throughput on one MI355X.
+
+Workload (the L = 16 LDS-resident shape): 2048 Gaussian-coupling samples
+(couplings on the 2^-18 grid), L = 16, 24 temperatures geometric in
+T = [0.4, 1.5], two replicas per temperature, h = 0.1, overlap measurement
+every 10 sweeps (measuring from the first sweep, so the timed region is the
+production measuring phase).  Inputs are seeded synthetic arrays, resident in
+HBM before timing starts.
+
+One step = one chunk of 100 sweeps of the whole batch: 2 x 100 checkerboard
+half-sweeps of every walker, 100 replica-exchange passes, 10 overlap
+measurements of every slot.  The metric is spin-flip attempts per ns
+(one attempt = one Metropolis trial at one site of one walker).
+
+Prints one JSON line (rank 0).  Besides the headline value it reports the
+unbatched form (the same kernels, one launch per sample, on a 64-sample subset),
+the roofline of the dominant kernel from HIP events recorded around each of
+its launches, and the CPU oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-flip attempts/ns at L=16 batched vs unbatched; bit-exact spins"
+SWEEPS_PER_STEP = 100
+KERNEL = {"L16_gauss": "row_sweep_kernel<16, 0>", "L8_gauss": "row_sweep_kernel<8, 0>",
+          "L4_gauss": "site_sweep_kernel<4, 0, 0>", "mixed_L6_12": "site/row sweep kernels (4 sizes)",
+          "L32_pm1": "hbm_half_kernel<32, 1, 0> x 2 + exchange + snapshot per sweep"}
+WORKLOAD_TEXT = {
+    "L16_gauss": "L16_gauss: L=16, 2048 samples, 24 temperatures geometric in T=[0.4,1.5], 2 replicas, "
+                 "Gaussian J on the 2^-18 grid, h=0.1, measure every 10 sweeps",
+    "L4_gauss": "L4_gauss: L=4, 16 samples, 8 temperatures in T=[0.5,2.0], 2 replicas, Gaussian J, h=0.3",
+    "L8_gauss": "L8_gauss: L=8, 1024 samples, 16 temperatures in T=[0.6,1.6], 2 replicas, Gaussian J, h=0.2",
+    "mixed_L6_12": "mixed_L6_12: 4096 samples, L in {6,8,10,12}, h in {0.1,0.2,0.3}, 16 temperatures in "
+                   "T=[0.5,1.6], 2 replicas, Gaussian J",
+    "L32_pm1": "L32_pm1: L=32, 512 samples, 32 temperatures in T=[0.5,2.0], 2 replicas, +-1 J, h=0.4, "
+               "HBM-resident",
+}
+
+# Algorithmic VALU work of one Metropolis attempt, in full-rate 32-bit lane
+# operations (a quarter-rate 32x32->64 multiply counts 4).  Common part:
+# Philox4x32-10 per 4 attempts = 10 rounds x (2 multiplies x 4 + 2 three-input
+# xors) = 100 -> 25; accept test 2; spin update 1; energy/magnetisation
+# bookkeeping 2.
+#   Gaussian couplings: local field 6 signed terms + h = 12; energy change and
+#   its scaling by beta 2; exponential (reduction 5, degree-7 Horner 14,
+#   scaling 2) 21; uniform from the random word 2            -> 67
+#   +-1 couplings: local field 6 sign products + count 6; threshold-table
+#   index and read 2                                          -> 38
+ALG_OPS_PER_ATTEMPT = {0: 67, 1: 38}
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: non-packed 32-bit VALU lane-ops/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def progress(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(work, n_samples, attempts):
+    from oracle import ea_oracle as O
+    threads = min(16, os.cpu_count() or 1)
+    sub = work.subset(range(min(n_samples, work.n_samples)))
+    n_samples = sub.n_samples
+    sweeps = max(1, int(round(attempts / sub.attempts_per_sweep())))
+    ens = O.OracleEnsemble(sub)
+    t0 = time.perf_counter()
+    ens.run(sweeps, threads=threads)
+    dt = time.perf_counter() - t0
+    attempts = sub.attempts_per_sweep() * sweeps
+    return {"value": attempts / dt / 1e9, "unit": "attempts/ns", "cores": threads, "kind": "oracle",
+            "sample": "%d of the %d samples x %d sweeps (%.3g attempts), %.1f s wall on %d threads"
+                      % (n_samples, work.n_samples, sweeps, attempts, dt, threads)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="L16_gauss",
+                    help="L16_gauss (default), L4_gauss, L8_gauss, mixed_L6_12 or L32_pm1")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--unbatched-samples", type=int, default=64)
+    ap.add_argument("--unbatched-steps", type=int, default=2)
+    ap.add_argument("--cpu-samples", type=int, default=64)
+    ap.add_argument("--cpu-attempts", type=float, default=7.5e8,
+                    help="size of the CPU oracle sample (about 10-30 s of single-core work per 1e8)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-unbatched", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time candidate plans first (the L=16 row engine has no thread-count knob)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="before timing, run a plain device-to-device copy of this many bytes "
+                         "(a reference kernel of known traffic for hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: every disorder sample is independent, so more GPUs "
+              "would each run their own share of samples; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1403_4560_amd import binding, workload as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    work = W.config_workload(args.workload, measure_start=0, measure_every=10)
+    ens = binding.Ensemble(work, stream=stream.cuda_stream)
+    ens.set_plan(chunk=SWEEPS_PER_STEP)
+    plan = ens.autotune(trial_sweeps=4) if args.autotune else ens.get_plan()
+    ens.set_plan(chunk=SWEEPS_PER_STEP)
+    attempts_per_step = work.attempts_per_sweep() * SWEEPS_PER_STEP
+    progress("ensemble ready, plan threads=%d" % plan.threads)
+
+    for _ in range(args.warmup):
+        ens.sweep_pt(SWEEPS_PER_STEP)
+    ens.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ens.sweep_pt(SWEEPS_PER_STEP)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_launches = ens.kernel_time()
+    ens.set_timing(False)
+    assert ens.check_energies() == 0, "incremental energies diverged"
+    value = attempts_per_step * args.steps / (dt * 1e9)
+    ens.close()
+    progress("timed %d steps in %.2f s: %.1f attempts/ns" % (args.steps, dt, value))
+
+    # roofline of the dominant kernel (the LDS-resident row-engine sweep kernel)
+    avg_launch_s = k_ms / 1e3 / max(k_launches, 1)
+    attempts_per_launch = attempts_per_step  # one launch per step (chunk)
+    ops = ALG_OPS_PER_ATTEMPT[work.jkind]
+    achieved = attempts_per_launch * ops / avg_launch_s / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "kernel": KERNEL.get(args.workload, "sweep kernels"), "avg_launch_ms": avg_launch_s * 1e3,
+                "ops_per_attempt": ops}
+
+    unbatched = None
+    if not args.no_unbatched:
+        sub = work.subset(range(min(args.unbatched_samples, work.n_samples)))
+        ub = binding.Ensemble(sub, stream=stream.cuda_stream)
+        ub.set_plan(chunk=SWEEPS_PER_STEP, threads=plan.threads)
+        ub.sweep_pt_unbatched(SWEEPS_PER_STEP)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.unbatched_steps):
+            ub.sweep_pt_unbatched(SWEEPS_PER_STEP)
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t1
+        ub.close()
+        ub_value = sub.attempts_per_sweep() * SWEEPS_PER_STEP * args.unbatched_steps / (dt1 * 1e9)
+        progress("unbatched: %.1f attempts/ns" % ub_value)
+        unbatched = {"value": ub_value, "unit": "attempts/ns", "samples": sub.n_samples,
+                     "sweeps": SWEEPS_PER_STEP * args.unbatched_steps,
+                     "batched_over_unbatched": value / ub_value}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(work, args.cpu_samples, args.cpu_attempts)
+        progress("cpu oracle: %.4f attempts/ns" % cpu["value"])
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "attempts/ns", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
+                   "sweeps_per_step": SWEEPS_PER_STEP, "samples": work.n_samples,
+                   "attempts_per_step": attempts_per_step, "threads_per_workgroup": plan.threads,
+                   "parallelism": "samples x chains across workgroups"},
+        "unbatched": unbatched,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

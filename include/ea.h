@@ -75,7 +75,7 @@ enum { EA_NACC = 36, EA_NPLANE = 9 };
 typedef struct {
     int32_t n_samples;           /* S >= 1                                      */
     const uint32_t *sample_id;   /* [S] Philox address word 3; NULL => 0..S-1   */
-    const int32_t *L;            /* [S] even, 2 <= L <= 64                      */
+    const int32_t *L;            /* [S] even, 2 <= L <= 32                      */
     const int32_t *n_temps;      /* [S] 1 <= n_T <= 64                          */
     const double *beta;          /* concat [S][n_T]: finite, > 0, non-decreasing */
     const float *h;              /* [S] uniform field, finite                    */
@@ -88,7 +88,13 @@ typedef struct {
     int32_t measure_every;       /* m >= 1, or 0 = never measure                */
     int64_t measure_start;       /* measure after sweep n iff n+1 > start and
                                     (n+1-start) % m == 0                         */
+    int32_t tier;                /* EA_TIER_AUTO: chains that fit LDS (L <= 16)
+                                    stay there, larger ones in HBM (L divisible
+                                    by 8); EA_TIER_HBM: every sample whose L is
+                                    divisible by 8 runs HBM-resident            */
 } ea_desc;
+
+enum { EA_TIER_AUTO = 0, EA_TIER_HBM = 1 };
 
 /* Launch plan.  Every plan gives bit-identical results. */
 typedef struct {
@@ -104,6 +110,10 @@ typedef struct {
  * spins not +-1, couplings off their alphabet, bad beta, bad m/start),
  * EA_ENOMEM, EA_EDEVICE. */
 ea_status ea_create_ensemble(const ea_desc *desc, void *hip_stream, ea_ensemble **out);
+/* Lattice sizes: every even L in [2, 16] runs LDS-resident (one workgroup per
+ * (sample, chain) holding the chain for a chunk of sweeps); L in {24, 32} (and
+ * 8, 16 under EA_TIER_HBM) runs HBM-resident (four launches per sweep).  Other
+ * sizes above 16 return EA_EUNSUPPORTED. */
 
 /* Advance every sample by n_sweeps sweeps (half-sweep p=0, half-sweep p=1,
  * replica exchange, measurement if due; Methods).  Asynchronous on the bound
@@ -195,6 +205,16 @@ ea_status ea_synchronize(ea_ensemble *ens);
 /* Sizes: samples, total slots (sum n_T), device bytes held. */
 ea_status ea_query(const ea_ensemble *ens, int32_t *n_samples, int64_t *total_slots,
                    int64_t *device_bytes);
+
+/* Device self-check of the acceptance shortcut used by the sweep kernels: for
+ * every binary32 x in [-86, 0] (1.1e9 values) the hardware estimate
+ * a = 2^(x log2 e) must bracket the in-house exponential,
+ * a (1 - 2^-16) <= exp_ea32(x) <= a (1 + 2^-16), so that comparing a uniform
+ * with the bracket decides exactly as comparing it with exp_ea32(x) whenever it
+ * falls outside, and the exact value is computed otherwise.  *violations must
+ * be 0; *max_rel_dev is the largest |a/exp_ea32(x) - 1| seen.  Synchronizing;
+ * uses the current device. */
+ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev);
 
 void ea_destroy(ea_ensemble *ens);
 const char *ea_last_error(void);

@@ -42,7 +42,8 @@ class Desc(ctypes.Structure):
                 ("spins0", ctypes.c_void_p),
                 ("seed", ctypes.c_uint64),
                 ("measure_every", ctypes.c_int32),
-                ("measure_start", ctypes.c_int64)]
+                ("measure_start", ctypes.c_int64),
+                ("tier", ctypes.c_int32)]
 
 
 class Plan(ctypes.Structure):
@@ -72,6 +73,7 @@ _SIGS = [
     ("ea_kernel_time", ctypes.c_int, [_VP, _VP, _VP]),
     ("ea_synchronize", ctypes.c_int, [_VP]),
     ("ea_query", ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    ("ea_verify_exp_bracket", ctypes.c_int, [_VP, _VP]),
     ("ea_destroy", None, [_VP]),
     ("ea_last_error", ctypes.c_char_p, []),
 ]
@@ -97,6 +99,14 @@ def _check(st):
         raise EAError(st, load().ea_last_error().decode(errors="replace"))
 
 
+def verify_exp_bracket():
+    """(violations, max relative deviation) of the acceptance shortcut."""
+    v = ctypes.c_int64()
+    m = ctypes.c_double()
+    _check(load().ea_verify_exp_bracket(ctypes.byref(v), ctypes.byref(m)))
+    return v.value, m.value
+
+
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -108,7 +118,7 @@ class Ensemble:
     (e.g. ``torch.cuda.current_stream().cuda_stream``) or None for a stream
     owned by the ensemble."""
 
-    def __init__(self, work, stream=None):
+    def __init__(self, work, stream=None, tier=0):
         lib = load()
         self.work = work
         self.S = work.n_samples
@@ -123,7 +133,7 @@ class Ensemble:
         k = self._keep
         d = Desc(self.S, _p(k["sid"]).value, _p(k["L"]).value, _p(k["nT"]).value, _p(k["beta"]).value,
                  _p(k["h"]).value, int(work.jkind), _p(k["J"]).value, _p(k["spins"]).value,
-                 int(work.seed), int(work.measure_every), int(work.measure_start))
+                 int(work.seed), int(work.measure_every), int(work.measure_start), int(tier))
         h = ctypes.c_void_p()
         _check(lib.ea_create_ensemble(ctypes.byref(d), ctypes.c_void_p(stream) if stream else None,
                                       ctypes.byref(h)))

@@ -21,14 +21,19 @@
 #include "ea_types.hpp"
 
 namespace ea {
-template <int JK> __global__ void lds_sweep_kernel(SweepArgs A);
+template <int L, int JK, int VAR> __global__ void site_sweep_kernel(SweepArgs A);
+template <int L, int VAR> __global__ void row_sweep_kernel(SweepArgs A);
+template <int L, int JK, int VAR> __global__ void hbm_half_kernel(SweepArgs A);
+__global__ void hbm_exchange_kernel(SweepArgs A);
+__global__ void hbm_snapshot_kernel(SweepArgs A);
 __global__ void measure_kernel(MeasureArgs A);
 __global__ void advance_kernel(int64_t *state, int64_t k);
+__global__ void exp_bracket_kernel(uint32_t, uint32_t, unsigned long long *, unsigned int *);
 template <int JK>
 __global__ void energy_kernel(const SampleDev *, const int32_t *, const int8_t *, const void *, int64_t *,
                               int32_t *);
 __global__ void snapshot_kernel(const SampleDev *, const int32_t *, const int8_t *, const int32_t *,
-                                const int64_t *, const int32_t *, int, int8_t *, double *);
+                                const int64_t *, const int32_t *, int, uint32_t *, double *);
 __global__ void finalize_kernel(const SampleDev *, int, int, int, const double *, double *);
 }  // namespace ea
 
@@ -53,8 +58,9 @@ struct SampleHost {
     int L, nT, N;
     uint32_t id;
     float h;
-    int64_t spin_off, J_off;
+    int64_t spin_off, J_off, frame_off;
     int32_t slot_off;
+    bool hbm;
 };
 
 struct DevBuf {
@@ -71,18 +77,31 @@ struct ea_ensemble {
     int32_t m = 0;
     int64_t mstart = 0;
     std::vector<SampleHost> smp;
-    int64_t total_slots = 0, spin_bytes = 0, J_elems = 0;
+    int64_t total_slots = 0, spin_bytes = 0, J_elems = 0, frame_words = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool dead = false;
     int64_t sweep = 0;
     ea_plan plan{};
-    size_t lds_needed = 0;
     int device = 0;
     // device buffers
     DevBuf samples, items, spins, J, beta, beta32, lut, was, EJ, M, flips, swaps, acc, frames, frameE,
-        state, slot_sample, costab, sintab, scratchE, scratchM, finout;
+        state, slot_sample, costab, sintab, scratchE, scratchM, finout, walkers, dEJ, dM, sow, Ju;
     int64_t frames_cap = 0;  // frames allocated
+    // launch classes: items sorted by lattice size, one launch per size
+    struct Class {
+        int L, begin, count, threads;
+        bool row;
+        size_t lds;
+        bool hbm;
+        int wbegin, wcount;  // HBM tier: range of the walker table
+    };
+    std::vector<Class> classes;
+    std::vector<int> item_pos;  // sample -> index of its chain-a item in the sorted item list
+    std::vector<int> sample_class;
+    std::vector<int> sorted_samples;
+    std::vector<int> walker_pos;  // sample -> first entry in the walker table (HBM tier)
+    bool any_hbm = false;
     std::map<int, hipGraphExec_t> graphs;
     std::map<int, hipGraph_t> graph_defs;
     // timing
@@ -213,7 +232,8 @@ void destroy_all(ea_ensemble *e)
     DevBuf *bufs[] = {&e->samples, &e->items, &e->spins, &e->J, &e->beta, &e->beta32, &e->lut,
                       &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->frames,
                       &e->frameE, &e->state, &e->slot_sample, &e->costab, &e->sintab,
-                      &e->scratchE, &e->scratchM, &e->finout};
+                      &e->scratchE, &e->scratchM, &e->finout, &e->walkers, &e->dEJ, &e->dM,
+                      &e->sow, &e->Ju};
     for (DevBuf *b : bufs) dfree(*b);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
@@ -238,7 +258,7 @@ ea_status ensure_frames(ea_ensemble *e, int K)
     e->device_bytes -= (int64_t)(e->frames.bytes + e->frameE.bytes);
     dfree(e->frames);
     dfree(e->frameE);
-    ea_status st = dalloc(e, e->frames, (size_t)(need * e->spin_bytes));
+    ea_status st = dalloc(e, e->frames, (size_t)(need * e->frame_words) * sizeof(uint32_t));
     if (st) return st;
     st = dalloc(e, e->frameE, (size_t)(need * 2 * e->total_slots) * sizeof(double));
     if (st) return st;
@@ -263,15 +283,20 @@ SweepArgs sweep_args(const ea_ensemble *e, int K, const int32_t *items, int n_it
     A.M = (int32_t *)e->M.p;
     A.flips = (int64_t *)e->flips.p;
     A.swaps = (int64_t *)e->swaps.p;
-    A.frames = (int8_t *)e->frames.p;
+    A.frames = (uint32_t *)e->frames.p;
     A.frameE = (double *)e->frameE.p;
-    A.frame_bytes = e->spin_bytes;
+    A.frame_words = e->frame_words;
     A.total_slots = e->total_slots;
     A.state = (const int64_t *)e->state.p;
     A.key0 = (uint32_t)e->seed;
     A.key1 = (uint32_t)(e->seed >> 32);
     A.measure_every = e->m;
     A.measure_start = e->mstart;
+    A.dEJ = (int64_t *)e->dEJ.p;
+    A.dM = (int32_t *)e->dM.p;
+    A.sow = (int32_t *)e->sow.p;
+    A.Ju = (const int32_t *)e->Ju.p;
+    A.jkind = e->jkind;
     return A;
 }
 
@@ -280,9 +305,9 @@ MeasureArgs measure_args(const ea_ensemble *e, int K, int explicit_frames)
     MeasureArgs M{};
     M.samples = (const SampleDev *)e->samples.p;
     M.slot_sample = (const int32_t *)e->slot_sample.p;
-    M.frames = (const int8_t *)e->frames.p;
+    M.frames = (const uint32_t *)e->frames.p;
     M.frameE = (const double *)e->frameE.p;
-    M.frame_bytes = e->spin_bytes;
+    M.frame_words = e->frame_words;
     M.total_slots = e->total_slots;
     M.acc = (double *)e->acc.p;
     M.costab = (const double *)e->costab.p;
@@ -295,14 +320,83 @@ MeasureArgs measure_args(const ea_ensemble *e, int K, int explicit_frames)
     return M;
 }
 
-hipError_t launch_sweep(ea_ensemble *e, int K, const int32_t *items, int n_items)
+using SweepFn = void (*)(SweepArgs);
+
+template <int VAR>
+SweepFn site_fn(int L, int jk)
 {
-    SweepArgs A = sweep_args(e, K, items, n_items);
-    dim3 grid(n_items), block(e->plan.threads);
-    if (e->jkind == EA_J_GAUSS_F32)
-        hipLaunchKernelGGL(lds_sweep_kernel<0>, grid, block, e->lds_needed, e->stream, A);
-    else
-        hipLaunchKernelGGL(lds_sweep_kernel<1>, grid, block, e->lds_needed, e->stream, A);
+#define EA_CASE(Lv) \
+    case Lv: return jk == 0 ? site_sweep_kernel<Lv, 0, VAR> : site_sweep_kernel<Lv, 1, VAR>;
+    switch (L) {
+        EA_CASE(2) EA_CASE(4) EA_CASE(6) EA_CASE(8) EA_CASE(10) EA_CASE(12) EA_CASE(14) EA_CASE(16)
+    default: return nullptr;
+    }
+#undef EA_CASE
+}
+
+SweepFn sweep_fn(int L, int jk, bool row, bool unbatched)
+{
+    if (row) {
+        if (L == 8) return unbatched ? row_sweep_kernel<8, 1> : row_sweep_kernel<8, 0>;
+        if (L == 16) return unbatched ? row_sweep_kernel<16, 1> : row_sweep_kernel<16, 0>;
+        return nullptr;
+    }
+    return unbatched ? site_fn<1>(L, jk) : site_fn<0>(L, jk);
+}
+
+// The row engine serves L = 8 and 16 with Gaussian couplings when a
+// workgroup can hold one thread per (walker, column).
+bool row_engine(int L, int nT, int jk)
+{
+    return jk == 0 && (L == 8 || L == 16) && ((nT * (L / 8) * L + 63) / 64) * 64 <= ROW_MAX_THREADS;
+}
+
+SweepFn hbm_fn(int L, int jk, bool unbatched)
+{
+#define EA_CASE(Lv)                                                                                \
+    case Lv:                                                                                       \
+        if (unbatched) return jk == 0 ? hbm_half_kernel<Lv, 0, 1> : hbm_half_kernel<Lv, 1, 1>;    \
+        return jk == 0 ? hbm_half_kernel<Lv, 0, 0> : hbm_half_kernel<Lv, 1, 0>;
+    switch (L) {
+        EA_CASE(8) EA_CASE(16) EA_CASE(24) EA_CASE(32)
+    default: return nullptr;
+    }
+#undef EA_CASE
+}
+
+bool hbm_size(int L) { return L == 8 || L == 16 || L == 24 || L == 32; }
+
+// One sweep of an HBM-tier range: half-sweep p = 0, p = 1, exchange, snapshot.
+hipError_t launch_hbm_sweep(ea_ensemble *e, int L, int it, int item_first, int n_items, int w_first, int n_walk,
+                            bool unbatched)
+{
+    SweepArgs A = sweep_args(e, 0, (const int32_t *)e->items.p + item_first, n_items);
+    A.walkers = (const int32_t *)e->walkers.p + w_first;
+    A.n_walkers = n_walk;
+    A.it = it;
+    SweepFn fn = hbm_fn(L, e->jkind, unbatched);
+    if (!fn) return hipErrorInvalidDeviceFunction;
+    const int G = L * L * L / 8, TILE = G < 1024 ? G : 1024, TPW = (G + TILE - 1) / TILE;
+    for (int p = 0; p < 2; ++p) {
+        A.p = p;
+        hipLaunchKernelGGL(fn, dim3(n_walk * TPW), dim3(256), 0, e->stream, A);
+        hipError_t st = hipGetLastError();
+        if (st != hipSuccess) return st;
+    }
+    hipLaunchKernelGGL(hbm_exchange_kernel, dim3(n_items), dim3(64), 0, e->stream, A);
+    hipError_t st = hipGetLastError();
+    if (st != hipSuccess) return st;
+    hipLaunchKernelGGL(hbm_snapshot_kernel, dim3(n_walk), dim3(256), 0, e->stream, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_class(ea_ensemble *e, const ea_ensemble::Class &c, int K, int first, int n_items, bool unbatched)
+{
+    SweepArgs A = sweep_args(e, K, (const int32_t *)e->items.p + first, n_items);
+    SweepFn fn = sweep_fn(c.L, e->jkind, c.row, unbatched);
+    if (!fn) return hipErrorInvalidDeviceFunction;
+    const int threads = c.row ? c.threads : e->plan.threads;
+    hipLaunchKernelGGL(fn, dim3(n_items), dim3(threads), c.lds, e->stream, A);
     return hipGetLastError();
 }
 
@@ -311,7 +405,6 @@ hipError_t launch_sweep(ea_ensemble *e, int K, const int32_t *items, int n_items
 hipError_t enqueue_chunk(ea_ensemble *e, int K, bool unbatched)
 {
     hipError_t st;
-    const int32_t *items = (const int32_t *)e->items.p;
     std::pair<hipEvent_t, hipEvent_t> ev{};
     if (e->timing) {
         if (e->ev_free.empty()) {
@@ -326,16 +419,31 @@ hipError_t enqueue_chunk(ea_ensemble *e, int K, bool unbatched)
         if ((st = hipEventRecord(ev.first, e->stream)) != hipSuccess) return st;
     }
     if (unbatched) {
-        for (int s = 0; s < e->S; ++s)
-            if ((st = launch_sweep(e, K, items + 2 * s, 2)) != hipSuccess) return st;
+        for (int s = 0; s < e->S; ++s) {
+            const auto &c = e->classes[e->sample_class[s]];
+            if (c.hbm) {
+                for (int it = 0; it < K; ++it)
+                    if ((st = launch_hbm_sweep(e, c.L, it, e->item_pos[s], 2, e->walker_pos[s], 2 * e->smp[s].nT,
+                                               true)) != hipSuccess)
+                        return st;
+            } else if ((st = launch_class(e, c, K, e->item_pos[s], 2, true)) != hipSuccess) {
+                return st;
+            }
+        }
     } else {
-        if ((st = launch_sweep(e, K, items, 2 * e->S)) != hipSuccess) return st;
+        for (const auto &c : e->classes)
+            if (!c.hbm && (st = launch_class(e, c, K, c.begin, c.count, false)) != hipSuccess) return st;
+        for (int it = 0; it < K && e->any_hbm; ++it)
+            for (const auto &c : e->classes)
+                if (c.hbm &&
+                    (st = launch_hbm_sweep(e, c.L, it, c.begin, c.count, c.wbegin, c.wcount, false)) != hipSuccess)
+                    return st;
     }
     if (e->timing && (st = hipEventRecord(ev.second, e->stream)) != hipSuccess) return st;
     const int64_t nmeas = measurements_upto(e->sweep + K, e->m, e->mstart) - measurements_upto(e->sweep, e->m, e->mstart);
     if (nmeas > 0 || e->plan.use_graph) {
         MeasureArgs M = measure_args(e, K, 0);
-        hipLaunchKernelGGL(measure_kernel, dim3((unsigned)e->total_slots), dim3(256), 0, e->stream, M);
+        hipLaunchKernelGGL(measure_kernel, dim3((unsigned)e->total_slots), dim3(64), 0, e->stream, M);
         if ((st = hipGetLastError()) != hipSuccess) return st;
     }
     hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, e->stream, (int64_t *)e->state.p, (int64_t)K);
@@ -410,9 +518,8 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         return fail(EA_EDEVICE, "no HIP device");
     }
     const size_t lds_max = max_lds_bytes();
-    int64_t soff = 0, joff = 0;
+    int64_t soff = 0, joff = 0, foff = 0;
     int32_t toff = 0;
-    size_t lds_need = 0;
     for (int s = 0; s < e->S; ++s) {
         SampleHost h{};
         h.L = d->L[s];
@@ -423,22 +530,27 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         h.spin_off = soff;
         h.J_off = joff;
         h.slot_off = toff;
+        h.frame_off = foff;
         const size_t need = lds_offsets(h.L, h.nT, e->jkind).total;
-        if (h.L > LDS_MAX_L || need > lds_max) {
+        const bool fits = h.L <= LDS_MAX_L && need <= lds_max;
+        h.hbm = !fits || (d->tier == EA_TIER_HBM && hbm_size(h.L));
+        if (h.hbm && !hbm_size(h.L)) {
             destroy_all(e);
-            return fail(EA_EUNSUPPORTED, "sample %d: L=%d with %d temperatures needs %zu B of LDS (limit %zu, L <= %d)",
-                        s, h.L, h.nT, need, lds_max, LDS_MAX_L);
+            return fail(EA_EUNSUPPORTED,
+                        "sample %d: L=%d with %d temperatures does not fit LDS (%zu of %zu B) and the HBM tier "
+                        "needs L in {8, 16, 24, 32}", s, h.L, h.nT, need, lds_max);
         }
-        lds_need = std::max(lds_need, need);
+        e->any_hbm |= h.hbm;
         soff += 2 * (int64_t)h.nT * h.N;
         joff += 3 * (int64_t)h.N;
+        foff += 2 * (int64_t)h.nT * h.L * h.L;
         toff += h.nT;
         e->smp.push_back(h);
     }
     e->total_slots = toff;
     e->spin_bytes = soff;
     e->J_elems = joff;
-    e->lds_needed = lds_need;
+    e->frame_words = foff;
 
     if (hip_stream) {
         e->stream = (hipStream_t)hip_stream;
@@ -449,12 +561,46 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         }
         e->own_stream = true;
     }
-    hipError_t fa = hipFuncSetAttribute((const void *)lds_sweep_kernel<0>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
-    if (fa == hipSuccess)
-        fa = hipFuncSetAttribute((const void *)lds_sweep_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds_max);
-    (void)fa;  // not every runtime needs (or accepts) the opt-in; launches report real failures
+    // launch classes: one per lattice size, items (2s, 2s+1) kept adjacent
+    {
+        std::vector<int> order(e->S);
+        for (int s = 0; s < e->S; ++s) order[s] = s;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const SampleHost &x = e->smp[a], &y = e->smp[b];
+            return x.hbm != y.hbm ? y.hbm : x.L < y.L;
+        });
+        e->item_pos.assign(e->S, 0);
+        e->sample_class.assign(e->S, 0);
+        e->walker_pos.assign(e->S, 0);
+        int wtotal = 0;
+        for (int i = 0; i < e->S; ++i) {
+            const SampleHost &h = e->smp[order[i]];
+            if (e->classes.empty() || e->classes.back().L != h.L || e->classes.back().hbm != h.hbm)
+                e->classes.push_back({h.L, 2 * i, 0, 0, !h.hbm, 0, h.hbm, wtotal, 0});
+            ea_ensemble::Class &c = e->classes.back();
+            c.count += 2;
+            if (h.hbm) {
+                e->walker_pos[order[i]] = wtotal;
+                c.wcount += 2 * h.nT;
+                wtotal += 2 * h.nT;
+            }
+            c.lds = std::max(c.lds, lds_offsets(h.L, h.nT, e->jkind).total);
+            c.row = c.row && row_engine(h.L, h.nT, e->jkind);
+            const int TW = (h.L / 8) * h.L;
+            c.threads = std::max(c.threads, ((h.nT * std::max(TW, 1) + 63) / 64) * 64);
+            e->item_pos[order[i]] = 2 * i;
+            e->sample_class[order[i]] = (int)e->classes.size() - 1;
+        }
+        for (const auto &c : e->classes) {
+            if (c.hbm) continue;
+            for (int v = 0; v < 2; ++v) {
+                SweepFn fn = sweep_fn(c.L, e->jkind, c.row, v == 1);
+                if (fn) (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)lds_max);
+            }
+        }
+        e->sorted_samples = order;
+    }
 
     // host-side layouts
     const int S = e->S;
@@ -470,9 +616,14 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     for (int s = 0; s < S; ++s) {
         const SampleHost &h = e->smp[s];
         const int N = h.N, HALF = N / 2;
-        sd[s] = SampleDev{h.L, h.nT, h.id, h.h, h.spin_off, h.J_off, h.slot_off, 0};
-        items[2 * s] = 2 * s;
-        items[2 * s + 1] = 2 * s + 1;
+        uint32_t down_mask = 0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 7; ++b)
+                if (2.0 * (a ? 1.0 : -1.0) * ((2.0 * b - 6.0) + (double)h.h) <= 0.0) down_mask |= 1u << (a * 7 + b);
+        sd[s] = SampleDev{h.L, h.nT, h.id, h.h, h.spin_off, h.J_off, h.slot_off, h.hbm ? 1 : 0, h.frame_off,
+                          down_mask, 0};
+        items[e->item_pos[s]] = 2 * s;
+        items[e->item_pos[s] + 1] = 2 * s + 1;
         for (int t = 0; t < h.nT; ++t) {
             slot_sample[h.slot_off + t] = s;
             beta[h.slot_off + t] = d->beta[h.slot_off + t];
@@ -505,6 +656,20 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
                         lut[((size_t)(h.slot_off + t) * 2 + a) * 7 + b] = v;
                     }
         }
+    }
+    // HBM tier: walker table (sample << 7 | chain << 6 | walker), couplings in 2^-18 units
+    std::vector<int32_t> wtab;
+    for (int i = 0; i < S; ++i) {
+        const int s = e->sorted_samples[i];
+        if (!e->smp[s].hbm) continue;
+        for (int r = 0; r < 2; ++r)
+            for (int w = 0; w < e->smp[s].nT; ++w) wtab.push_back((s << 7) | (r << 6) | w);
+    }
+    std::vector<int32_t> Ju;
+    if (e->any_hbm && e->jkind == EA_J_GAUSS_F32) {
+        Ju.resize(e->J_elems);
+        const float *Jf = (const float *)Jsub.data();
+        for (int64_t i = 0; i < e->J_elems; ++i) Ju[i] = (int32_t)(Jf[i] * 262144.0f);
     }
     std::vector<double> costab((MAX_L + 1) * MAX_L, 0.0), sintab((MAX_L + 1) * MAX_L, 0.0);
     for (int L = 1; L <= MAX_L; ++L)
@@ -541,6 +706,11 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     ALLOC(costab, sizeof(double) * costab.size());
     ALLOC(sintab, sizeof(double) * sintab.size());
     ALLOC(finout, sizeof(double) * MAX_T * EA_NOBS);
+    ALLOC(dEJ, sizeof(int64_t) * 2 * TS);
+    ALLOC(dM, sizeof(int32_t) * 2 * TS);
+    ALLOC(sow, sizeof(int32_t) * 2 * TS);
+    ALLOC(walkers, sizeof(int32_t) * wtab.size());
+    ALLOC(Ju, sizeof(int32_t) * Ju.size());
 #undef ALLOC
     {
         ea_status fs = ensure_frames(e, e->plan.chunk);
@@ -566,13 +736,18 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     H2D(lut, lut.data(), sizeof(uint32_t) * 14 * TS);
     H2D(was, was.data(), sizeof(int32_t) * 2 * TS);
     H2D(slot_sample, slot_sample.data(), sizeof(int32_t) * TS);
+    H2D(sow, was.data(), sizeof(int32_t) * 2 * TS);  // identity, like walker_at_slot
+    if (!wtab.empty()) H2D(walkers, wtab.data(), sizeof(int32_t) * wtab.size());
+    if (!Ju.empty()) H2D(Ju, Ju.data(), sizeof(int32_t) * Ju.size());
     H2D(costab, costab.data(), sizeof(double) * costab.size());
     H2D(sintab, sintab.data(), sizeof(double) * sintab.size());
 #undef H2D
     if (hipMemsetAsync(e->flips.p, 0, e->flips.bytes, e->stream) != hipSuccess ||
         hipMemsetAsync(e->swaps.p, 0, e->swaps.bytes, e->stream) != hipSuccess ||
         hipMemsetAsync(e->acc.p, 0, e->acc.bytes, e->stream) != hipSuccess ||
-        hipMemsetAsync(e->state.p, 0, e->state.bytes, e->stream) != hipSuccess) {
+        hipMemsetAsync(e->state.p, 0, e->state.bytes, e->stream) != hipSuccess ||
+        hipMemsetAsync(e->dEJ.p, 0, e->dEJ.bytes, e->stream) != hipSuccess ||
+        hipMemsetAsync(e->dM.p, 0, e->dM.bytes, e->stream) != hipSuccess) {
         destroy_all(e);
         return fail(EA_EDEVICE, "memset failed");
     }
@@ -616,11 +791,11 @@ ea_status ea_measure(ea_ensemble *e, int32_t flags, double *acc, int64_t *flips,
         if (st) return st;
         hipLaunchKernelGGL(snapshot_kernel, dim3(2 * e->S), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
                            (const int32_t *)e->items.p, (const int8_t *)e->spins.p, (const int32_t *)e->was.p,
-                           (const int64_t *)e->EJ.p, (const int32_t *)e->M.p, e->jkind, (int8_t *)e->frames.p,
+                           (const int64_t *)e->EJ.p, (const int32_t *)e->M.p, e->jkind, (uint32_t *)e->frames.p,
                            (double *)e->frameE.p);
         HIP_TRY(e, hipGetLastError());
         MeasureArgs M = measure_args(e, 0, 1);
-        hipLaunchKernelGGL(measure_kernel, dim3((unsigned)e->total_slots), dim3(256), 0, e->stream, M);
+        hipLaunchKernelGGL(measure_kernel, dim3((unsigned)e->total_slots), dim3(64), 0, e->stream, M);
         HIP_TRY(e, hipGetLastError());
     }
     if (acc) HIP_TRY(e, hipMemcpyAsync(acc, e->acc.p, e->acc.bytes, hipMemcpyDeviceToHost, e->stream));
@@ -686,6 +861,7 @@ ea_status ea_write_state(ea_ensemble *e, const int8_t *spins_in, int64_t sweep)
     }
     HIP_TRY(e, hipMemcpyAsync(e->spins.p, sp.data(), e->spin_bytes, hipMemcpyHostToDevice, e->stream));
     HIP_TRY(e, hipMemcpyAsync(e->was.p, was.data(), e->was.bytes, hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(e->sow.p, was.data(), e->sow.bytes, hipMemcpyHostToDevice, e->stream));
     int64_t sw = sweep;
     HIP_TRY(e, hipMemcpyAsync(e->state.p, &sw, sizeof sw, hipMemcpyHostToDevice, e->stream));
     if (e->jkind == EA_J_GAUSS_F32)
@@ -825,9 +1001,10 @@ ea_status ea_autotune(ea_ensemble *e, int32_t trial_sweeps)
     if (!usable(e)) return EA_ESTATE;
     if (trial_sweeps < 1) return fail(EA_EINVAL, "trial_sweeps must be >= 1");
     // back up the mutable state, time each candidate, restore
-    DevBuf *mut[] = {&e->spins, &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->state};
-    std::vector<DevBuf> bak(8);
-    for (int i = 0; i < 8; ++i) {
+    DevBuf *mut[] = {&e->spins, &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->state, &e->sow};
+    constexpr int NMUT = sizeof mut / sizeof mut[0];
+    std::vector<DevBuf> bak(NMUT);
+    for (int i = 0; i < NMUT; ++i) {
         ea_status st = dalloc(e, bak[i], mut[i]->bytes);
         if (st) {
             for (auto &b : bak) dfree(b);
@@ -863,7 +1040,7 @@ ea_status ea_autotune(ea_ensemble *e, int32_t trial_sweeps)
             best = orig;
             best.threads = cand[c];
         }
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < NMUT; ++i)
             HIP_TRY(e, hipMemcpyAsync(mut[i]->p, bak[i].p, mut[i]->bytes, hipMemcpyDeviceToDevice, e->stream));
         e->sweep = sweep0;
     }
@@ -892,6 +1069,39 @@ ea_status ea_query(const ea_ensemble *e, int32_t *n_samples, int64_t *total_slot
     if (n_samples) *n_samples = e->S;
     if (total_slots) *total_slots = e->total_slots;
     if (device_bytes) *device_bytes = e->device_bytes;
+    return EA_OK;
+}
+
+ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev)
+{
+    if (!violations || !max_rel_dev) return fail(EA_EINVAL, "null argument");
+    const uint32_t first = 0x80000000u;                 // -0.0
+    const uint32_t last = 0xC2AC0000u;                  // -86.0
+    const uint32_t count = last - first + 1;
+    unsigned long long *dv = nullptr;
+    unsigned int *dm = nullptr;
+    if (hipMalloc(&dv, sizeof *dv) != hipSuccess) return fail(EA_ENOMEM, "hipMalloc failed");
+    if (hipMalloc(&dm, sizeof *dm) != hipSuccess) {
+        (void)hipFree(dv);
+        return fail(EA_ENOMEM, "hipMalloc failed");
+    }
+    hipError_t st = hipMemset(dv, 0, sizeof *dv);
+    if (st == hipSuccess) st = hipMemset(dm, 0, sizeof *dm);
+    if (st == hipSuccess) {
+        hipLaunchKernelGGL(exp_bracket_kernel, dim3((count + 255) / 256), dim3(256), 0, nullptr, first, count, dv, dm);
+        st = hipGetLastError();
+    }
+    unsigned long long v = 0;
+    unsigned int m = 0;
+    if (st == hipSuccess) st = hipMemcpy(&v, dv, sizeof v, hipMemcpyDeviceToHost);
+    if (st == hipSuccess) st = hipMemcpy(&m, dm, sizeof m, hipMemcpyDeviceToHost);
+    (void)hipFree(dv);
+    (void)hipFree(dm);
+    if (st != hipSuccess) return fail(EA_EDEVICE, "bracket check failed: %s", hipGetErrorString(st));
+    float mf;
+    std::memcpy(&mf, &m, sizeof mf);
+    *violations = (int64_t)v;
+    *max_rel_dev = (double)mf;
     return EA_OK;
 }
 

@@ -2,16 +2,24 @@
 //
 // LDS-resident tier (L <= 16).  One workgroup owns one (sample, chain) work
 // item for a chunk of K sweeps: the chain's n_T walkers (int8 spins) and the
-// sample's couplings (float32 or int8) are loaded into LDS once, then every
-// sweep of the chunk -- two checkerboard half-sweeps of Metropolis updates
-// (Methods: single-spin-flip Monte Carlo), the exact energy bookkeeping, the
-// replica-exchange pass (Methods: parallel tempering) and, when due, a
-// snapshot of the chain in slot order for the overlap measurement -- runs out
-// of LDS.  Spins and maps go back to HBM once per chunk.
+// sample's couplings are loaded into LDS once, then every sweep of the chunk --
+// two checkerboard half-sweeps of Metropolis updates (Methods: single-spin-flip
+// Monte Carlo), the exact energy bookkeeping, the replica-exchange pass
+// (Methods: parallel tempering) and, when due, a snapshot of the chain in slot
+// order for the overlap measurement -- runs out of LDS.  Spins and maps go back
+// to HBM once per chunk.
 //
 // The two chains of a sample only meet in the overlap q_i = s_i^a s_i^b
 // (eq. 2), so they are independent work items; the measurement kernel
 // combines their snapshots after the chunk.
+//
+// Two half-sweep engines share that frame:
+//  * row engine (L = 8, 16; Gaussian couplings): a thread owns one walker and
+//    one (x-word, y) column and walks z; it works on 4 sites at once (one int8x4
+//    word = one Philox call), keeps couplings as integer 2^-18 units and the
+//    walker's energy/flip tallies in registers for the whole sweep;
+//  * site engine (any even L <= 16, either coupling kind): a thread takes a
+//    4-site group of any walker and updates its sites one by one.
 #include "ea_device.hpp"
 #include "ea_types.hpp"
 
@@ -50,15 +58,66 @@ __device__ __forceinline__ int wave_sum_i32(int v)
     return v;
 }
 
-// One checkerboard half-sweep (parity p) over every walker of the chain.  A
-// thread takes groups of four consecutive sublattice sites (one Philox call,
-// word h&3 for site h) of one walker; sites of one parity never neighbour each
-// other, so the updates of a half-sweep are independent.
+// Sum over aligned groups of W consecutive lanes (W a power of two <= 64).
+template <int W>
+__device__ __forceinline__ long long group_sum_i64(long long v)
+{
+#pragma unroll
+    for (int m = W / 2; m >= 1; m >>= 1) {
+        const int lo = __shfl_xor((int)(unsigned long long)v, m);
+        const int hi = __shfl_xor((int)((unsigned long long)v >> 32), m);
+        v += (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    }
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ int group_sum_i32(int v)
+{
+#pragma unroll
+    for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// Pointers into the dynamic LDS of one work item.
+struct ItemLds {
+    int8_t *S;
+    void *J;
+    int32_t *was, *sow, *M, *dM, *fl, *sw;
+    long long *EJ, *dEJ;
+    uint32_t *lut;
+    float *b32;
+    double *b64;
+};
+
+__device__ __forceinline__ ItemLds item_lds(char *smem, int L, int nT, int jkind)
+{
+    const LdsOff o = lds_offsets(L, nT, jkind);
+    ItemLds p;
+    p.S = (int8_t *)(smem + o.spins);
+    p.J = (void *)(smem + o.J);
+    p.was = (int32_t *)(smem + o.was);
+    p.sow = (int32_t *)(smem + o.sow);
+    p.M = (int32_t *)(smem + o.M);
+    p.dM = (int32_t *)(smem + o.dM);
+    p.fl = (int32_t *)(smem + o.fl);
+    p.sw = (int32_t *)(smem + o.sw);
+    p.EJ = (long long *)(smem + o.EJ);
+    p.dEJ = (long long *)(smem + o.dEJ);
+    p.lut = (uint32_t *)(smem + o.lut);
+    p.b32 = (float *)(smem + o.b32);
+    p.b64 = (double *)(smem + o.b64);
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Site engine: one checkerboard half-sweep (parity p) over every walker of the
+// chain.  A thread takes groups of four consecutive sublattice sites (one
+// Philox call, word h&3 for site h) of one walker; sites of one parity never
+// neighbour each other, so the updates of a half-sweep are independent.
 template <int L, int JK>
-__device__ __forceinline__ void half_sweep(const SweepArgs &A, const SampleDev &d, int r, int p,
-                                           int64_t n, int8_t *S, const void *Jl, const int32_t *sow,
-                                           int32_t *dM, int32_t *fl, long long *dEJ,
-                                           const uint32_t *lut, const float *b32)
+__device__ __forceinline__ void site_half_sweep(const SweepArgs &A, const SampleDev &d, int r, int p,
+                                                int64_t n, const ItemLds &I)
 {
     constexpr int N = L * L * L, HALF = N / 2, G = HALF / 4, HL = L / 2;
     const int nT = d.n_T;
@@ -74,12 +133,12 @@ __device__ __forceinline__ void half_sweep(const SweepArgs &A, const SampleDev &
         int t = 0;
         int dEu = 0, dm = 0, nfl = 0;
         if (act) {
-            t = sow[w];
+            t = I.sow[w];
             const u32x4 rw = philox4x32_10((uint32_t)g, c1, c2base | ((uint32_t)t << 1), d.sample_id,
                                            A.key0, A.key1);
             const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
-            int8_t *Sp = S + (size_t)w * N + p * HALF;
-            const int8_t *So = S + (size_t)w * N + (1 - p) * HALF;
+            int8_t *Sp = I.S + (size_t)w * N + p * HALF;
+            const int8_t *So = I.S + (size_t)w * N + (1 - p) * HALF;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int h = 4 * g + i;
@@ -99,8 +158,8 @@ __device__ __forceinline__ void half_sweep(const SweepArgs &A, const SampleDev &
                 bool accept;
                 int units;
                 if constexpr (JK == 0) {
-                    const float *Jp = (const float *)Jl + p * 3 * HALF;
-                    const float *Jo = (const float *)Jl + (1 - p) * 3 * HALF;
+                    const float *Jp = (const float *)I.J + p * 3 * HALF;
+                    const float *Jo = (const float *)I.J + (1 - p) * 3 * HALF;
                     // exact: every partial sum is a multiple of 2^-18 below 2^6
                     float SJ = Jp[h] * (float)s0;
                     SJ = SJ + Jo[hxm] * (float)s1;
@@ -110,18 +169,18 @@ __device__ __forceinline__ void half_sweep(const SweepArgs &A, const SampleDev &
                     SJ = SJ + Jo[2 * HALF + hzm] * (float)s5;
                     const float f = SJ + d.h32;
                     const float dE = (2.0f * (float)si) * f;
-                    const float e = exp_ea32(-(b32[t] * dE));
+                    const float e = exp_ea32(-(I.b32[t] * dE));
                     accept = (dE <= 0.0f) | (u24_of(words[i]) < e);
                     units = (int)(SJ * 262144.0f);
                 } else {
-                    const int8_t *Jp = (const int8_t *)Jl + p * 3 * HALF;
-                    const int8_t *Jo = (const int8_t *)Jl + (1 - p) * 3 * HALF;
+                    const int8_t *Jp = (const int8_t *)I.J + p * 3 * HALF;
+                    const int8_t *Jo = (const int8_t *)I.J + (1 - p) * 3 * HALF;
                     const int SJ = Jp[h] * s0 + Jo[hxm] * s1 + Jp[HALF + h] * s2 +
                                    Jo[HALF + hym] * s3 + Jp[2 * HALF + h] * s4 +
                                    Jo[2 * HALF + hzm] * s5;
                     const float f = (float)SJ + d.h32;  // sign of SJ + h is exact
                     const bool down = si * f <= 0.0f;
-                    const uint32_t thr = lut[(t * 2 + ((si + 1) >> 1)) * 7 + ((SJ + 6) >> 1)];
+                    const uint32_t thr = I.lut[(t * 2 + ((si + 1) >> 1)) * 7 + ((SJ + 6) >> 1)];
                     accept = down | (words[i] < thr);
                     units = SJ;
                 }
@@ -142,53 +201,227 @@ __device__ __forceinline__ void half_sweep(const SweepArgs &A, const SampleDev &
                 const int pk = wave_sum_i32(nfl + dm * 65536);
                 if ((tid & 63) == 0) {
                     const int sfl = pk & 0xFFFF;
-                    atomicAdd((unsigned long long *)&dEJ[w0], (unsigned long long)se);
-                    atomicAdd(&dM[w0], (pk - sfl) / 65536);
-                    atomicAdd(&fl[sow[w0]], sfl);
+                    atomicAdd((unsigned long long *)&I.dEJ[w0], (unsigned long long)se);
+                    atomicAdd(&I.dM[w0], (pk - sfl) / 65536);
+                    atomicAdd(&I.fl[I.sow[w0]], sfl);
                 }
             }
         } else if (act) {
-            atomicAdd((unsigned long long *)&dEJ[w], (unsigned long long)(long long)dEu);
-            atomicAdd(&dM[w], dm);
-            atomicAdd(&fl[t], nfl);
+            atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)(long long)dEu);
+            atomicAdd(&I.dM[w], dm);
+            atomicAdd(&I.fl[t], nfl);
         }
     }
 }
 
-template <int L, int JK>
-__device__ void run_item(const SweepArgs &A, const SampleDev &d, int r, char *smem)
+// ---------------------------------------------------------------------------
+// Metropolis update of one int8x4 word: four sites of one sublattice row with
+// their six neighbour words (aligned and shifted x, +y, -y, +z, -z; bytes +-1)
+// and their six bonds (int32 multiples of 2^-18).  rw holds the four Philox
+// words of the group, m2b = -2 beta32 of the walker's slot.  Returns the flip
+// mask (0xFE in the bytes of accepted sites) and adds (S_u XOR m) over
+// accepted sites to accE, m = 0 for s_i = +1 and -1 for s_i = -1.
+//
+// Decision: x = -fl32(beta32 dE) is formed as fl32((-2 beta32 s_i) f) (the same
+// real number, rounded once), dE <= 0 iff x >= 0, exp_ea32 is 0 below -86.  A
+// uniform U = w >> 8 below a (1 - 2^-16) 2^24 or at or above a (1 + 2^-16) 2^24,
+// with a = 2^(x log2 e) from the hardware exponential, is decided by the
+// bracket (ea_verify_exp_bracket proves it contains exp_ea32 for every x);
+// otherwise by U 2^-24 < exp_ea32(x) itself.
+__device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, uint32_t Xs, uint32_t Yp,
+                                                      uint32_t Ym, uint32_t Zp, uint32_t Zm, const int Ja[4],
+                                                      const int Js[4], const int Jy[4], const int Jyn[4],
+                                                      const int Jz[4], const int Jzn[4], const u32x4 rw,
+                                                      float m2b, float h32, int &accE)
+{
+    const float LOG2E = __uint_as_float(0x3FB8AA3Bu);
+    const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
+    uint32_t fm = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int sh = 8 * i;
+        int Su = __mul24(__builtin_amdgcn_sbfe((int)Xa, sh, 8), Ja[i]);
+        Su += __mul24(__builtin_amdgcn_sbfe((int)Xs, sh, 8), Js[i]);
+        Su += __mul24(__builtin_amdgcn_sbfe((int)Yp, sh, 8), Jy[i]);
+        Su += __mul24(__builtin_amdgcn_sbfe((int)Ym, sh, 8), Jyn[i]);
+        Su += __mul24(__builtin_amdgcn_sbfe((int)Zp, sh, 8), Jz[i]);
+        Su += __mul24(__builtin_amdgcn_sbfe((int)Zm, sh, 8), Jzn[i]);
+        // f = fl32(S_J + h): S_J = Su 2^-18 exactly, so the fused form rounds once, as the sum does
+        const float f = __builtin_fmaf((float)Su, 0x1p-18f, h32);
+        const int m = __builtin_amdgcn_sbfe((int)Sv, sh + 7, 1);  // 0: s_i = +1, -1: s_i = -1
+        const float c = m ? -m2b : m2b;                            // -2 beta s_i, exact
+        const float x = c * f;                                     // = -fl32(beta * dE)
+        const bool down = x >= 0.0f;                               // dE <= 0
+        const bool big = x < -86.0f;                               // exp_ea32 returns 0
+        const float xn = fminf(x, 0.0f);
+        const float a = __builtin_amdgcn_exp2f(xn * LOG2E);
+        const float U = (float)(words[i] >> 8);
+        const bool accf = U < a * 16776960.0f;   // a (1 - 2^-16) 2^24
+        const bool rejf = U >= a * 16777472.0f;  // a (1 + 2^-16) 2^24
+        bool accept = down | (!big & accf);
+        if (!down & !big & !accf & !rejf) accept = U * 0x1p-24f < exp_ea32(x);
+        if (accept) {
+            fm |= 0xFEu << sh;
+            accE += Su ^ m;
+        }
+    }
+    return fm;
+}
+
+// The same for +-1 couplings (int8x4 bond words Ja..Jzn): a bond-spin product
+// byte n ^ J is 0x00 for +1 and 0xFE for -1, so per byte c = number of -1
+// products and S_J = 6 - 2c.  Acceptance uses the slot's threshold table
+// thr[a*7 + b] (a = (s_i+1)/2, b = (S_J+6)/2): accept iff dE <= 0 (bit a*7+b of
+// down_mask, set on the host from 2 s (S_J + h) <= 0) or w < thr.  S_u = S_J.
+__device__ __forceinline__ uint32_t update_word_pm1(uint32_t Sv, uint32_t Xa, uint32_t Xs, uint32_t Yp, uint32_t Ym,
+                                                    uint32_t Zp, uint32_t Zm, uint32_t Ja, uint32_t Js, uint32_t Jy,
+                                                    uint32_t Jyn, uint32_t Jz, uint32_t Jzn, const u32x4 rw,
+                                                    const uint32_t *thr, uint32_t down_mask, int &accE)
+{
+    constexpr uint32_t LOW = 0x01010101u;
+    const uint32_t cnt = (((Xa ^ Ja) >> 1) & LOW) + (((Xs ^ Js) >> 1) & LOW) + (((Yp ^ Jy) >> 1) & LOW) +
+                         (((Ym ^ Jyn) >> 1) & LOW) + (((Zp ^ Jz) >> 1) & LOW) + (((Zm ^ Jzn) >> 1) & LOW);
+    const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
+    uint32_t fm = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int sh = 8 * i;
+        const int b = 6 - (int)((cnt >> sh) & 0xFFu);               // (S_J + 6) / 2
+        const int m = __builtin_amdgcn_sbfe((int)Sv, sh + 7, 1);  // 0: s_i = +1, -1: s_i = -1
+        const int idx = (m + 1) * 7 + b;
+        const bool accept = ((down_mask >> idx) & 1u) | (words[i] < thr[idx]);
+        if (accept) {
+            fm |= 0xFEu << sh;
+            accE += (2 * b - 6) ^ m;
+        }
+    }
+    return fm;
+}
+
+// ---------------------------------------------------------------------------
+// Row engine (L = 8 or 16, Gaussian couplings held as int32 multiples of
+// 2^-18).  Sublattice p's row (y, z) holds L/2 sites, i.e. L/8 int8x4 words;
+// site h = 4g + i of the row's word g sits at x = 2(4k + i) + eps with
+// eps = (y + z + p) & 1.  Its x-neighbours in the other sublattice are the
+// sites of the same word index ("aligned", x + 1 if eps = 0, else x - 1) and
+// the sites one position over ("shifted": x - 1 if eps = 0, else x + 1), which
+// one byte permute of the row's words produces.  The y and z neighbours are
+// the words of the same index in the adjacent rows.
+//
+// Tallies per thread and sweep: accE = sum over accepted sites of
+// (S_u XOR m) with m = 0 for s_i = +1 and -1 for s_i = -1, so that
+// sum of s_i S_u = accE + (accepted down spins); bf and bd count the set bits
+// of the flip masks (7 per flipped byte) and of (spins AND flip mask).
+template <int L>
+__device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleDev &d, int r, int p,
+                                               int64_t n, const ItemLds &I, int w, int y, int k, int t,
+                                               int &accE, int &bf, int &bd)
+{
+    constexpr int N = L * L * L, HALF = N / 2, WPR = L / 8, HL = L / 2;
+    constexpr int PLANE = L * HL;  // bytes of one z-plane of one sublattice
+    const int yp = (y + 1) & (L - 1), ym = (y - 1) & (L - 1);
+    const int kx = WPR == 2 ? (k ^ 1) : k;
+    const int o_y0 = 4 * (y * WPR + k), o_yp = 4 * (yp * WPR + k), o_ym = 4 * (ym * WPR + k);
+    const int o_x = 4 * (y * WPR + kx);
+    const int e_prev = y * HL + (k == 0 ? HL - 1 : 4 * k - 1);  // element before the word, cyclic
+    const uint8_t *own = (const uint8_t *)I.S + (size_t)w * N + p * HALF;
+    const uint8_t *oth = (const uint8_t *)I.S + (size_t)w * N + (1 - p) * HALF;
+    uint8_t *ownw = (uint8_t *)I.S + (size_t)w * N + p * HALF;
+    const int *Jp = (const int *)I.J + p * 3 * HALF;        // own bonds +x,+y,+z
+    const int *Jo = (const int *)I.J + (1 - p) * 3 * HALF;  // other sublattice's bonds
+    const uint32_t c1 = (uint32_t)(2 * n + p);
+    const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
+    const float m2b = -2.0f * I.b32[t];
+    const float h32 = d.h32;
+#pragma unroll 1
+    for (int z = 0; z < L; ++z) {
+        const int zp = (z + 1) & (L - 1), zm = (z - 1) & (L - 1);
+        const int eps = (y + z + p) & 1;
+        const uint32_t Sv = *(const uint32_t *)(own + o_y0 + z * PLANE);
+        const uint32_t Xa = *(const uint32_t *)(oth + o_y0 + z * PLANE);
+        const uint32_t Xo = *(const uint32_t *)(oth + o_x + z * PLANE);
+        const uint32_t Yp = *(const uint32_t *)(oth + o_yp + z * PLANE);
+        const uint32_t Ym = *(const uint32_t *)(oth + o_ym + z * PLANE);
+        const uint32_t Zp = *(const uint32_t *)(oth + o_y0 + zp * PLANE);
+        const uint32_t Zm = *(const uint32_t *)(oth + o_y0 + zm * PLANE);
+        const uint32_t Xs = __builtin_amdgcn_perm(Xa, Xo, eps ? 0x00070605u : 0x06050403u);
+        const int4 Jpx = *(const int4 *)(Jp + o_y0 + z * PLANE);
+        const int4 Jpy = *(const int4 *)(Jp + HALF + o_y0 + z * PLANE);
+        const int4 Jpz = *(const int4 *)(Jp + 2 * HALF + o_y0 + z * PLANE);
+        const int4 V = *(const int4 *)(Jo + o_y0 + z * PLANE);
+        const int4 Jym = *(const int4 *)(Jo + HALF + o_ym + z * PLANE);
+        const int4 Jzm = *(const int4 *)(Jo + 2 * HALF + o_y0 + zm * PLANE);
+        const int Ep = Jo[e_prev + z * PLANE];
+        // bond to the aligned x-neighbour and to the shifted one
+        const int Ja[4] = {eps ? V.x : Jpx.x, eps ? V.y : Jpx.y, eps ? V.z : Jpx.z, eps ? V.w : Jpx.w};
+        const int Js[4] = {eps ? Jpx.x : Ep, eps ? Jpx.y : V.x, eps ? Jpx.z : V.y, eps ? Jpx.w : V.z};
+        const int Jy[4] = {Jpy.x, Jpy.y, Jpy.z, Jpy.w}, Jyn[4] = {Jym.x, Jym.y, Jym.z, Jym.w};
+        const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
+        const uint32_t g = (uint32_t)(o_y0 / 4 + z * (PLANE / 4));
+        const u32x4 rw = philox4x32_10(g, c1, c2, d.sample_id, A.key0, A.key1);
+        const uint32_t fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b,
+                                              h32, accE);
+        *(uint32_t *)(ownw + o_y0 + z * PLANE) = Sv ^ fm;
+        bf += __builtin_popcount(fm);
+        bd += __builtin_popcount(Sv & fm);
+    }
+}
+
+// One snapshot row: bit x set iff the spin at (x, y, z) is -1, for the row
+// index row = y + L z of a walker held in LDS in sublattice layout.
+template <int L>
+__device__ __forceinline__ uint32_t pack_row_lds(const int8_t *Sw, int row)
+{
+    constexpr int HALF = L * L * L / 2;
+    const int yz = (row % L) + row / L;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int x = 0; x < L; ++x) {
+        const int p = (x + yz) & 1;
+        bits |= (uint32_t)(Sw[p * HALF + ((x + L * row) >> 1)] < 0) << x;
+    }
+    return bits;
+}
+
+// ---------------------------------------------------------------------------
+// The per-item frame shared by both engines.
+template <int L, int JK, bool ROW>
+__device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d, int r, char *smem)
 {
     constexpr int N = L * L * L;
     const int nT = d.n_T;
     const int T = blockDim.x, tid = threadIdx.x;
-    const LdsOff o = lds_offsets(L, nT, JK);
-    int8_t *S = (int8_t *)(smem + o.spins);
-    void *Jl = (void *)(smem + o.J);
-    int32_t *was = (int32_t *)(smem + o.was), *sow = (int32_t *)(smem + o.sow);
-    int32_t *Mw = (int32_t *)(smem + o.M), *dM = (int32_t *)(smem + o.dM);
-    int32_t *fl = (int32_t *)(smem + o.fl), *sw = (int32_t *)(smem + o.sw);
-    long long *EJ = (long long *)(smem + o.EJ), *dEJ = (long long *)(smem + o.dEJ);
-    uint32_t *lut = (uint32_t *)(smem + o.lut);
-    float *b32 = (float *)(smem + o.b32);
-    double *b64 = (double *)(smem + o.b64);
+    const ItemLds I = item_lds(smem, L, nT, JK);
 
     const size_t sbase = (size_t)d.spin_off + (size_t)r * nT * N;
     const int gi = 2 * d.slot_off + r * nT;
-    block_copy(S, A.spins + sbase, (size_t)nT * N);
-    block_copy(Jl, (const char *)A.J + (size_t)d.J_off * (JK == 0 ? 4 : 1),
-               (size_t)3 * N * (JK == 0 ? 4 : 1));
+    block_copy(I.S, A.spins + sbase, (size_t)nT * N);
+    if constexpr (ROW) {
+        // couplings as exact int32 multiples of 2^-18
+        const float *src = (const float *)A.J + d.J_off;
+        int *dst = (int *)I.J;
+        for (int i = tid; i < 3 * N; i += T) dst[i] = (int)(src[i] * 262144.0f);
+    } else {
+        block_copy(I.J, (const char *)A.J + (size_t)d.J_off * (JK == 0 ? 4 : 1),
+                   (size_t)3 * N * (JK == 0 ? 4 : 1));
+    }
     for (int i = tid; i < nT; i += T) {
-        was[i] = A.was[gi + i];
-        EJ[i] = A.EJ[gi + i];
-        Mw[i] = A.M[gi + i];
-        fl[i] = 0;
-        sw[i] = 0;
-        b32[i] = A.beta32[d.slot_off + i];
-        b64[i] = A.beta[d.slot_off + i];
+        I.was[i] = A.was[gi + i];
+        I.EJ[i] = A.EJ[gi + i];
+        I.M[i] = A.M[gi + i];
+        I.fl[i] = 0;
+        I.sw[i] = 0;
+        I.b32[i] = A.beta32[d.slot_off + i];
+        I.b64[i] = A.beta[d.slot_off + i];
     }
     if (JK == 1)
-        for (int i = tid; i < nT * 14; i += T) lut[i] = A.lut[(size_t)d.slot_off * 14 + i];
+        for (int i = tid; i < nT * 14; i += T) I.lut[i] = A.lut[(size_t)d.slot_off * 14 + i];
     __syncthreads();
+
+    // row engine: this thread's walker and column
+    constexpr int WPR = L / 8 > 0 ? L / 8 : 1, TW = WPR * L;
+    const int rw_w = tid / TW, rw_q = tid - rw_w * TW;
+    const int rw_k = rw_q % WPR, rw_y = rw_q / WPR;
 
     const double unit = JK == 0 ? 0x1p-18 : 1.0;
     const double hd = (double)d.h32;
@@ -197,28 +430,50 @@ __device__ void run_item(const SweepArgs &A, const SampleDev &d, int r, char *sm
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
         for (int i = tid; i < nT; i += T) {
-            sow[was[i]] = i;
-            dEJ[i] = 0;
-            dM[i] = 0;
+            I.sow[I.was[i]] = i;
+            I.dEJ[i] = 0;
+            I.dM[i] = 0;
         }
         __syncthreads();
-        half_sweep<L, JK>(A, d, r, 0, n, S, Jl, sow, dM, fl, dEJ, lut, b32);
-        __syncthreads();
-        half_sweep<L, JK>(A, d, r, 1, n, S, Jl, sow, dM, fl, dEJ, lut, b32);
+        if constexpr (ROW) {
+            // Barriers stay outside the walker test: a wave may hold lanes of
+            // an active and an idle walker.  A walker's TW lanes are aligned
+            // and all active or all idle, so the group sums see only its lanes.
+            const bool on = rw_w < nT;
+            const int t = on ? I.sow[rw_w] : 0;
+            int accE = 0, bf = 0, bd = 0;
+            if (on) row_half_sweep<L>(A, d, r, 0, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
+            __syncthreads();
+            if (on) {
+                row_half_sweep<L>(A, d, r, 1, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
+                const long long sE = group_sum_i64<TW>((long long)accE);
+                const int sf = group_sum_i32<TW>(bf), sd = group_sum_i32<TW>(bd);
+                if (rw_q == 0) {
+                    const int flips = sf / 7, ndown = sd / 7;
+                    I.dEJ[rw_w] = 2 * (sE + ndown);
+                    I.dM[rw_w] = -2 * (flips - 2 * ndown);
+                    I.fl[t] += flips;
+                }
+            }
+        } else {
+            site_half_sweep<L, JK>(A, d, r, 0, n, I);
+            __syncthreads();
+            site_half_sweep<L, JK>(A, d, r, 1, n, I);
+        }
         __syncthreads();
         for (int i = tid; i < nT; i += T) {
-            EJ[i] += dEJ[i];
-            Mw[i] += dM[i];
+            I.EJ[i] += I.dEJ[i];
+            I.M[i] += I.dM[i];
         }
         __syncthreads();
         // Replica exchange of neighbouring slots (t, t+1), t = n&1, n&1 + 2, ...
         for (int j = tid;; j += T) {
             const int t = (int)(n & 1) + 2 * j;
             if (t + 1 >= nT) break;
-            const int w0 = was[t], w1 = was[t + 1];
-            const double E0 = (double)EJ[w0] * unit - hd * (double)Mw[w0];
-            const double E1 = (double)EJ[w1] * unit - hd * (double)Mw[w1];
-            const double D = (b64[t] - b64[t + 1]) * (E0 - E1);
+            const int w0 = I.was[t], w1 = I.was[t + 1];
+            const double E0 = (double)I.EJ[w0] * unit - hd * (double)I.M[w0];
+            const double E1 = (double)I.EJ[w1] * unit - hd * (double)I.M[w1];
+            const double D = (I.b64[t] - I.b64[t + 1]) * (E0 - E1);
             bool acc = D >= 0.0;
             if (!acc) {
                 const u32x4 q = philox4x32_10(0u, (uint32_t)n,
@@ -227,9 +482,9 @@ __device__ void run_item(const SweepArgs &A, const SampleDev &d, int r, char *sm
                 acc = u53_of(q.x, q.y) < exp_ea64(D);
             }
             if (acc) {
-                was[t] = w1;
-                was[t + 1] = w0;
-                sw[t] += 1;
+                I.was[t] = w1;
+                I.was[t + 1] = w0;
+                I.sw[t] += 1;
             }
         }
         __syncthreads();
@@ -238,88 +493,314 @@ __device__ void run_item(const SweepArgs &A, const SampleDev &d, int r, char *sm
         if (A.measure_every > 0 && done > A.measure_start &&
             (done - A.measure_start) % A.measure_every == 0) {
             const int64_t f = measurements_upto(done, A.measure_every, A.measure_start) - cnt0 - 1;
-            int8_t *dst = A.frames + f * A.frame_bytes + sbase;
-            for (int t = 0; t < nT; ++t) block_copy(dst + (size_t)t * N, S + (size_t)was[t] * N, N);
+            uint32_t *dst = A.frames + f * A.frame_words + d.frame_off + (size_t)r * nT * L * L;
+            for (int i = tid; i < nT * L * L; i += T) {
+                const int t = i / (L * L), row = i - t * (L * L);
+                dst[i] = pack_row_lds<L>(I.S + (size_t)I.was[t] * N, row);
+            }
             for (int t = tid; t < nT; t += T) {
-                const int w = was[t];
-                A.frameE[f * 2 * A.total_slots + gi + t] = (double)EJ[w] * unit - hd * (double)Mw[w];
+                const int w = I.was[t];
+                A.frameE[f * 2 * A.total_slots + gi + t] = (double)I.EJ[w] * unit - hd * (double)I.M[w];
             }
         }
     }
     __syncthreads();
-    block_copy(A.spins + sbase, S, (size_t)nT * N);
+    block_copy(A.spins + sbase, I.S, (size_t)nT * N);
     for (int i = tid; i < nT; i += T) {
-        A.was[gi + i] = was[i];
-        A.EJ[gi + i] = EJ[i];
-        A.M[gi + i] = Mw[i];
-        A.flips[gi + i] += fl[i];
-        A.swaps[gi + i] += sw[i];
+        A.was[gi + i] = I.was[i];
+        A.EJ[gi + i] = I.EJ[i];
+        A.M[gi + i] = I.M[i];
+        A.flips[gi + i] += I.fl[i];
+        A.swaps[gi + i] += I.sw[i];
     }
     __syncthreads();
 }
 
-template <int JK>
-__global__ void __launch_bounds__(1024) lds_sweep_kernel(SweepArgs A)
+// One kernel per (engine, L, coupling kind).  VAR only separates the symbol
+// of the one-sample-per-launch comparator from the batched launch in
+// profiles; the code is identical.
+template <int L, int JK, int VAR>
+__global__ void __launch_bounds__(1024) site_sweep_kernel(SweepArgs A)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
         const int code = A.items[item];
-        const SampleDev d = A.samples[code >> 1];
-        const int r = code & 1;
-        switch (d.L) {
-        case 2: run_item<2, JK>(A, d, r, smem); break;
-        case 4: run_item<4, JK>(A, d, r, smem); break;
-        case 6: run_item<6, JK>(A, d, r, smem); break;
-        case 8: run_item<8, JK>(A, d, r, smem); break;
-        case 10: run_item<10, JK>(A, d, r, smem); break;
-        case 12: run_item<12, JK>(A, d, r, smem); break;
-        case 14: run_item<14, JK>(A, d, r, smem); break;
-        case 16: run_item<16, JK>(A, d, r, smem); break;
-        default: break;  // the host never schedules other sizes here
+        run_item<L, JK, false>(A, A.samples[code >> 1], code & 1, smem);
+    }
+}
+
+template <int L, int VAR>
+__global__ void __launch_bounds__(ROW_MAX_THREADS) row_sweep_kernel(SweepArgs A)
+{
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
+        const int code = A.items[item];
+        run_item<L, 0, true>(A, A.samples[code >> 1], code & 1, smem);
+    }
+}
+
+#define EA_SITE(Lv)                                               \
+    template __global__ void site_sweep_kernel<Lv, 0, 0>(SweepArgs); \
+    template __global__ void site_sweep_kernel<Lv, 1, 0>(SweepArgs); \
+    template __global__ void site_sweep_kernel<Lv, 0, 1>(SweepArgs); \
+    template __global__ void site_sweep_kernel<Lv, 1, 1>(SweepArgs);
+EA_SITE(2)
+EA_SITE(4)
+EA_SITE(6)
+EA_SITE(8)
+EA_SITE(10)
+EA_SITE(12)
+EA_SITE(14)
+EA_SITE(16)
+#undef EA_SITE
+template __global__ void row_sweep_kernel<8, 0>(SweepArgs);
+template __global__ void row_sweep_kernel<8, 1>(SweepArgs);
+template __global__ void row_sweep_kernel<16, 0>(SweepArgs);
+template __global__ void row_sweep_kernel<16, 1>(SweepArgs);
+
+// ---------------------------------------------------------------------------
+// HBM-resident tier (chains too large for LDS, e.g. L = 32).  Spins stay in
+// HBM in the same sublattice layout; each sweep is four launches: half-sweep
+// p = 0, half-sweep p = 1, exchange, snapshot.  A half-sweep workgroup takes a
+// tile of up to 1024 int8x4 words of one walker (4 per thread); energy,
+// magnetisation and flip tallies are reduced per workgroup and added to the
+// walker's per-sweep change with integer atomics (order-free).  Blocks of one
+// sample are kept on one XCD (blocks are dealt to the 8 XCDs round-robin) so
+// the sample's couplings stay in that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int nb8 = nb & ~7;
+    return b < nb8 ? (b & 7) * (nb8 >> 3) + (b >> 3) : b;
+}
+
+template <int W>
+__device__ __forceinline__ void block_sum3(long long &a, int &b, int &c)
+{
+    __shared__ long long sa[W / 64];
+    __shared__ int sb[W / 64], sc[W / 64];
+    a = wave_sum_i64(a);
+    b = wave_sum_i32(b);
+    c = wave_sum_i32(c);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[wv] = a;
+        sb[wv] = b;
+        sc[wv] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < W / 64; ++i) {
+            a += sa[i];
+            b += sb[i];
+            c += sc[i];
         }
     }
 }
 
-template __global__ void lds_sweep_kernel<0>(SweepArgs);
-template __global__ void lds_sweep_kernel<1>(SweepArgs);
-
-// ---------------------------------------------------------------------------
-// Overlap measurement (eq. 2).  One workgroup per (sample, slot): for each
-// snapshot frame of the chunk, in time order, form q_i = s_i^a s_i^b, the
-// integer sums S0 = sum q_i and the plane sums P_f[c] = sum of q_i over sites
-// with k_f . r = c (mod L) for the nine wave vectors, then
-// q(k_f) = sum_c P_f[c] e^{2 pi i c / L} / N (summed in c order) and add to
-// the binary64 accumulators of the slot in time order.
-__device__ __forceinline__ int plane_coord(int f, int L, int x, int y, int z)
+template <int L, int JK, int VAR>
+__global__ void __launch_bounds__(256) hbm_half_kernel(SweepArgs A)
 {
-    int c;
-    switch (f) {
-    case 0: c = x; break;
-    case 1: c = y; break;
-    case 2: c = z; break;
-    case 3: c = x + y; break;
-    case 4: c = x - y; break;
-    case 5: c = x + z; break;
-    case 6: c = x - z; break;
-    case 7: c = y + z; break;
-    default: c = y - z; break;
+    constexpr int N = L * L * L, HALF = N / 2, WPR = L / 8, HL = L / 2, G = HALF / 4;
+    constexpr int TILE = G < 1024 ? G : 1024, TPW = (G + TILE - 1) / TILE;
+    __shared__ uint32_t thr[14];
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int wi = b / TPW, tile = b - wi * TPW;
+    if (wi >= A.n_walkers) return;
+    const int code = A.walkers[wi];
+    const SampleDev d = A.samples[code >> 7];
+    const int r = (code >> 6) & 1, w = code & 63;
+    const int nT = d.n_T, gi = 2 * d.slot_off + r * nT;
+    const int t = A.sow[gi + w];
+    const int p = A.p;
+    const int64_t n = A.state[0] + A.it;
+    const int tid = threadIdx.x;
+    if (JK == 1 && tid < 14) thr[tid] = A.lut[((size_t)d.slot_off + t) * 14 + tid];
+    __syncthreads();
+    uint8_t *Sw = (uint8_t *)A.spins + d.spin_off + ((size_t)r * nT + w) * N;
+    uint8_t *own = Sw + p * HALF;
+    const uint8_t *oth = Sw + (1 - p) * HALF;
+    const uint32_t c1 = (uint32_t)(2 * n + p);
+    const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
+    const float m2b = -2.0f * A.beta32[d.slot_off + t];
+    int accE = 0, bf = 0, bd = 0;
+    for (int j = 0; j < (TILE + 255) / 256; ++j) {
+        const int g = tile * TILE + j * 256 + tid;
+        if (j * 256 + tid >= TILE || g >= G) break;
+        const int k = g % WPR, row = g / WPR, y = row % L, z = row / L;
+        const int eps = (y + z + p) & 1;
+        const int kx = eps ? (k + 1) % WPR : (k + WPR - 1) % WPR;
+        const int yp = (y + 1) % L, ym = (y + L - 1) % L, zp = (z + 1) % L, zm = (z + L - 1) % L;
+        const int g_x = row * WPR + kx;
+        const int g_yp = (yp + L * z) * WPR + k, g_ym = (ym + L * z) * WPR + k;
+        const int g_zp = (y + L * zp) * WPR + k, g_zm = (y + L * zm) * WPR + k;
+        const uint32_t Sv = *(const uint32_t *)(own + 4 * g);
+        const uint32_t Xa = *(const uint32_t *)(oth + 4 * g);
+        const uint32_t Xo = *(const uint32_t *)(oth + 4 * g_x);
+        const uint32_t Yp = *(const uint32_t *)(oth + 4 * g_yp);
+        const uint32_t Ym = *(const uint32_t *)(oth + 4 * g_ym);
+        const uint32_t Zp = *(const uint32_t *)(oth + 4 * g_zp);
+        const uint32_t Zm = *(const uint32_t *)(oth + 4 * g_zm);
+        const uint32_t sel = eps ? 0x00070605u : 0x06050403u;
+        const uint32_t Xs = __builtin_amdgcn_perm(Xa, Xo, sel);
+        const u32x4 rw = philox4x32_10((uint32_t)g, c1, c2, d.sample_id, A.key0, A.key1);
+        uint32_t fm;
+        if constexpr (JK == 0) {
+            const int *Jp = A.Ju + d.J_off + (size_t)p * 3 * HALF;
+            const int *Jo = A.Ju + d.J_off + (size_t)(1 - p) * 3 * HALF;
+            const int4 Jpx = *(const int4 *)(Jp + 4 * g);
+            const int4 Jpy = *(const int4 *)(Jp + HALF + 4 * g);
+            const int4 Jpz = *(const int4 *)(Jp + 2 * HALF + 4 * g);
+            const int4 V = *(const int4 *)(Jo + 4 * g);
+            const int4 Jym = *(const int4 *)(Jo + HALF + 4 * g_ym);
+            const int4 Jzm = *(const int4 *)(Jo + 2 * HALF + 4 * g_zm);
+            const int Ep = Jo[row * HL + (k == 0 ? HL - 1 : 4 * k - 1)];
+            const int Ja[4] = {eps ? V.x : Jpx.x, eps ? V.y : Jpx.y, eps ? V.z : Jpx.z, eps ? V.w : Jpx.w};
+            const int Js[4] = {eps ? Jpx.x : Ep, eps ? Jpx.y : V.x, eps ? Jpx.z : V.y, eps ? Jpx.w : V.z};
+            const int Jy[4] = {Jpy.x, Jpy.y, Jpy.z, Jpy.w}, Jyn[4] = {Jym.x, Jym.y, Jym.z, Jym.w};
+            const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
+            fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b, d.h32, accE);
+        } else {
+            const uint8_t *J8 = (const uint8_t *)A.J + d.J_off;
+            const uint8_t *Jp = J8 + (size_t)p * 3 * HALF, *Jo = J8 + (size_t)(1 - p) * 3 * HALF;
+            const uint32_t Jpx = *(const uint32_t *)(Jp + 4 * g);
+            const uint32_t Jpy = *(const uint32_t *)(Jp + HALF + 4 * g);
+            const uint32_t Jpz = *(const uint32_t *)(Jp + 2 * HALF + 4 * g);
+            const uint32_t V = *(const uint32_t *)(Jo + 4 * g);
+            const uint32_t Vo = *(const uint32_t *)(Jo + 4 * g_x);
+            const uint32_t Jym = *(const uint32_t *)(Jo + HALF + 4 * g_ym);
+            const uint32_t Jzm = *(const uint32_t *)(Jo + 2 * HALF + 4 * g_zm);
+            const uint32_t Ja = eps ? V : Jpx;
+            const uint32_t Js = eps ? Jpx : __builtin_amdgcn_perm(V, Vo, 0x06050403u);
+            fm = update_word_pm1(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jpy, Jym, Jpz, Jzm, rw, thr, d.down_mask,
+                                 accE);
+        }
+        *(uint32_t *)(own + 4 * g) = Sv ^ fm;
+        bf += __builtin_popcount(fm);
+        bd += __builtin_popcount(Sv & fm);
     }
-    c %= L;
-    return c < 0 ? c + L : c;
+    long long sE = accE;
+    block_sum3<256>(sE, bf, bd);
+    if (tid == 0) {
+        const int flips = bf / 7, ndown = bd / 7;
+        atomicAdd((unsigned long long *)&A.dEJ[gi + w], (unsigned long long)(2 * (sE + ndown)));
+        atomicAdd(&A.dM[gi + w], -2 * (flips - 2 * ndown));
+        atomicAdd((unsigned long long *)&A.flips[gi + t], (unsigned long long)flips);
+    }
 }
 
-__global__ void __launch_bounds__(256) measure_kernel(MeasureArgs A)
+// Exchange pass of one sweep for the HBM tier: one wave per (sample, chain).
+__global__ void __launch_bounds__(64) hbm_exchange_kernel(SweepArgs A)
 {
+    const int code = A.items[blockIdx.x];
+    const SampleDev d = A.samples[code >> 1];
+    const int r = code & 1;
+    const int nT = d.n_T, gi = 2 * d.slot_off + r * nT;
+    const int tid = threadIdx.x;
+    const int64_t n = A.state[0] + A.it;
+    const double unit = A.jkind == 0 ? 0x1p-18 : 1.0;
+    const double hd = (double)d.h32;
+    if (tid < nT) {
+        A.EJ[gi + tid] += A.dEJ[gi + tid];
+        A.M[gi + tid] += A.dM[gi + tid];
+        A.dEJ[gi + tid] = 0;
+        A.dM[gi + tid] = 0;
+    }
+    __syncthreads();
+    for (int j = tid;; j += blockDim.x) {
+        const int t = (int)(n & 1) + 2 * j;
+        if (t + 1 >= nT) break;
+        const int w0 = A.was[gi + t], w1 = A.was[gi + t + 1];
+        const double E0 = (double)A.EJ[gi + w0] * unit - hd * (double)A.M[gi + w0];
+        const double E1 = (double)A.EJ[gi + w1] * unit - hd * (double)A.M[gi + w1];
+        const double D = (A.beta[d.slot_off + t] - A.beta[d.slot_off + t + 1]) * (E0 - E1);
+        bool acc = D >= 0.0;
+        if (!acc) {
+            const u32x4 q = philox4x32_10(0u, (uint32_t)n,
+                                          (PURPOSE_EXCHANGE << 28) | ((uint32_t)t << 1) | (uint32_t)r,
+                                          d.sample_id, A.key0, A.key1);
+            acc = u53_of(q.x, q.y) < exp_ea64(D);
+        }
+        if (acc) {
+            A.was[gi + t] = w1;
+            A.was[gi + t + 1] = w0;
+            A.swaps[gi + t] += 1;
+        }
+    }
+    __syncthreads();
+    if (tid < nT) {
+        const int w = A.was[gi + tid];
+        A.sow[gi + w] = tid;
+        const int64_t done = n + 1;
+        if (A.measure_every > 0 && done > A.measure_start && (done - A.measure_start) % A.measure_every == 0) {
+            const int64_t f = measurements_upto(done, A.measure_every, A.measure_start) -
+                              measurements_upto(A.state[0], A.measure_every, A.measure_start) - 1;
+            A.frameE[f * 2 * A.total_slots + gi + tid] = (double)A.EJ[gi + w] * unit - hd * (double)A.M[gi + w];
+        }
+    }
+}
+
+// Snapshot of one (sample, chain, slot) for the HBM tier, when a measurement
+// is due after this sweep (the launch returns at once otherwise).
+__global__ void __launch_bounds__(256) hbm_snapshot_kernel(SweepArgs A)
+{
+    const int64_t n = A.state[0] + A.it, done = n + 1;
+    if (!(A.measure_every > 0 && done > A.measure_start && (done - A.measure_start) % A.measure_every == 0))
+        return;
+    const int code = A.walkers[blockIdx.x];
+    const SampleDev d = A.samples[code >> 7];
+    const int r = (code >> 6) & 1, t = code & 63;
+    const int L = d.L, L2 = L * L, N = L2 * L, HALF = N / 2;
+    const int nT = d.n_T, gi = 2 * d.slot_off + r * nT;
+    const int64_t f = measurements_upto(done, A.measure_every, A.measure_start) -
+                      measurements_upto(A.state[0], A.measure_every, A.measure_start) - 1;
+    const int8_t *Sw = A.spins + d.spin_off + ((size_t)r * nT + A.was[gi + t]) * N;
+    uint32_t *dst = A.frames + f * A.frame_words + d.frame_off + ((size_t)r * nT + t) * L2;
+    for (int row = threadIdx.x; row < L2; row += blockDim.x) {
+        const int yz = (row % L) + row / L;
+        uint32_t bits = 0;
+        for (int x = 0; x < L; ++x) {
+            const int p = (x + yz) & 1;
+            bits |= (uint32_t)(Sw[p * HALF + ((x + L * row) >> 1)] < 0) << x;
+        }
+        dst[row] = bits;
+    }
+}
+
+#define EA_HBM(Lv)                                                  \
+    template __global__ void hbm_half_kernel<Lv, 0, 0>(SweepArgs); \
+    template __global__ void hbm_half_kernel<Lv, 1, 0>(SweepArgs); \
+    template __global__ void hbm_half_kernel<Lv, 0, 1>(SweepArgs); \
+    template __global__ void hbm_half_kernel<Lv, 1, 1>(SweepArgs);
+EA_HBM(8)
+EA_HBM(16)
+EA_HBM(24)
+EA_HBM(32)
+#undef EA_HBM
+
+// ---------------------------------------------------------------------------
+// Overlap measurement (eq. 2).  One wave per (sample, slot).  For each snapshot
+// frame of the chunk, in time order: the overlap bits e = NOT(a XOR b) of the
+// two chains' rows mark q_i = +1; the column counts
+//   C[x][y] = #{z : e(x,y,z)},  D[x][z] = #{y : e(x,y,z)},  R[y][z] = #{x : e}
+// give the count of q_i = +1 in every plane of the nine wave vectors
+// k_f = (2 pi / L) u_f (each plane c = u_f . r mod L holds L^2 sites), so the
+// plane sums are P_f[c] = 2 count - L^2 and
+// q(k_f) = sum_c P_f[c] e^{2 pi i c / L} / N (summed in c order), added to the
+// binary64 accumulators of the slot in time order.
+__global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
+{
+    __shared__ uint32_t eqr[MAX_L * MAX_L];
+    __shared__ int C[MAX_L * MAX_L], D[MAX_L * MAX_L], R[MAX_L * MAX_L];
     __shared__ int P[NPLANE][MAX_L];
-    __shared__ int S0;
     __shared__ double accs[NACC];
     __shared__ double re_f[NPLANE], im_f[NPLANE];
     const int gs = blockIdx.x;
     const int s = A.slot_sample[gs];
     const SampleDev d = A.samples[s];
     const int t = gs - d.slot_off;
-    const int L = d.L, N = L * L * L, HALF = N / 2, HL = L / 2;
+    const int L = d.L, L2 = L * L;
     const int tid = threadIdx.x, T = blockDim.x;
+    const uint32_t mask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
     int64_t nf;
     if (A.explicit_frames > 0) {
         nf = A.explicit_frames;
@@ -330,25 +811,48 @@ __global__ void __launch_bounds__(256) measure_kernel(MeasureArgs A)
     }
     if (nf <= 0) return;
     for (int i = tid; i < NACC; i += T) accs[i] = A.acc[(size_t)gs * NACC + i];
-    const double Nd = (double)N;
+    const double Nd = (double)L2 * (double)L;
     for (int64_t f = 0; f < nf; ++f) {
-        for (int i = tid; i < NPLANE * MAX_L; i += T) (&P[0][0])[i] = 0;
-        if (tid == 0) S0 = 0;
-        __syncthreads();
-        const int8_t *sa = A.frames + f * A.frame_bytes + d.spin_off + (size_t)t * N;
-        const int8_t *sb = sa + (size_t)d.n_T * N;
-        int s0 = 0;
-        for (int idx = tid; idx < N; idx += T) {
-            const int p = idx >= HALF, h = idx - p * HALF;
-            const int row = h / HL, j = h - row * HL, y = row % L, z = row / L;
-            const int x = 2 * j + ((y + z + p) & 1);
-            const int q = (int)sa[idx] * (int)sb[idx];
-            s0 += q;
-#pragma unroll
-            for (int fam = 0; fam < NPLANE; ++fam) atomicAdd(&P[fam][plane_coord(fam, L, x, y, z)], q);
+        const uint32_t *ra = A.frames + f * A.frame_words + d.frame_off + (size_t)t * L2;
+        const uint32_t *rb = ra + (size_t)d.n_T * L2;
+        for (int i = tid; i < L2; i += T) {
+            const uint32_t e = ~(ra[i] ^ rb[i]) & mask;
+            eqr[i] = e;
+            R[i] = __builtin_popcount(e);
         }
-        s0 = wave_sum_i32(s0);
-        if ((tid & 63) == 0) atomicAdd(&S0, s0);
+        __syncthreads();
+        for (int e = tid; e < 2 * L2; e += T) {
+            const int e2 = e < L2 ? e : e - L2;
+            const int x = e2 / L, u = e2 - x * L;
+            int cnt = 0;
+            if (e < L2) {
+                for (int z = 0; z < L; ++z) cnt += (eqr[u + L * z] >> x) & 1u;  // u = y
+                C[e2] = cnt;
+            } else {
+                for (int y = 0; y < L; ++y) cnt += (eqr[y + L * u] >> x) & 1u;  // u = z
+                D[e2] = cnt;
+            }
+        }
+        __syncthreads();
+        for (int task = tid; task < NPLANE * L; task += T) {
+            const int fam = task / L, c = task - fam * L;
+            int cnt = 0;
+            for (int v = 0; v < L; ++v) {
+                const int cm = (c - v + L) % L, cp = (c + v) % L;
+                switch (fam) {
+                case 0: cnt += C[c * L + v]; break;           // x = c
+                case 1: cnt += C[v * L + c]; break;           // y = c
+                case 2: cnt += D[v * L + c]; break;           // z = c
+                case 3: cnt += C[cm * L + v]; break;          // x + y = c
+                case 4: cnt += C[cp * L + v]; break;          // x - y = c
+                case 5: cnt += D[cm * L + v]; break;          // x + z = c
+                case 6: cnt += D[cp * L + v]; break;          // x - z = c
+                case 7: cnt += R[v + L * cm]; break;          // y + z = c
+                default: cnt += R[v + L * ((v - c + L) % L)]; break;  // y - z = c
+                }
+            }
+            P[fam][c] = 2 * cnt - L2;
+        }
         __syncthreads();
         if (tid < NPLANE) {
             const double *ct = A.costab + (size_t)L * MAX_L, *st = A.sintab + (size_t)L * MAX_L;
@@ -367,6 +871,8 @@ __global__ void __launch_bounds__(256) measure_kernel(MeasureArgs A)
             accs[6 + 3 * tid] += im;
             accs[7 + 3 * tid] += re * re + im * im;
         } else if (tid == NPLANE) {
+            int S0 = 0;
+            for (int c = 0; c < L; ++c) S0 += P[0][c];
             const double q0 = (double)S0 / Nd;
             accs[0] += 1.0;
             accs[1] += q0;
@@ -383,6 +889,26 @@ __global__ void __launch_bounds__(256) measure_kernel(MeasureArgs A)
         __syncthreads();
     }
     for (int i = tid; i < NACC; i += T) A.acc[(size_t)gs * NACC + i] = accs[i];
+}
+
+// Exhaustive check of the acceptance bracket used by the row engine: for every
+// binary32 x in [-86, 0] the hardware estimate a = 2^(x log2 e) must satisfy
+// a (1 - 2^-16) <= exp_ea32(x) <= a (1 + 2^-16) in units of 2^-24, so that a
+// uniform below the lower bound is certainly accepted and one at or above the
+// upper bound certainly rejected by the exact test.
+__global__ void exp_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned long long *violations,
+                                   unsigned int *max_dev_bits)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float x = __uint_as_float(first_bits + i);
+    const float LOG2E = __uint_as_float(0x3FB8AA3Bu);
+    const float a = __builtin_amdgcn_exp2f(fminf(x, 0.0f) * LOG2E);
+    const float lo = a * 16776960.0f, hi = a * 16777472.0f;
+    const float E24 = exp_ea32(x) * 16777216.0f;
+    if (!(lo <= E24) || !(E24 <= hi)) atomicAdd(violations, 1ull);
+    const float dev = fabsf(a * 16777216.0f - E24) / E24;
+    atomicMax(max_dev_bits, __float_as_uint(dev));
 }
 
 __global__ void advance_kernel(int64_t *state, int64_t k)
@@ -456,20 +982,31 @@ template __global__ void energy_kernel<0>(const SampleDev *, const int32_t *, co
 template __global__ void energy_kernel<1>(const SampleDev *, const int32_t *, const int8_t *, const void *,
                                           int64_t *, int32_t *);
 
-// Snapshot of the current state (slot order) into frame 0, for an immediate
-// measurement.  One workgroup per (sample, chain).
+// Snapshot of the current state (slot order, bit rows) into frame 0, for an
+// immediate measurement.  One workgroup per (sample, chain).
 __global__ void __launch_bounds__(256) snapshot_kernel(const SampleDev *samples, const int32_t *items,
                                                       const int8_t *spins, const int32_t *was,
                                                       const int64_t *EJ, const int32_t *M, int jkind,
-                                                      int8_t *frame, double *frameE)
+                                                      uint32_t *frame, double *frameE)
 {
     const int code = items[blockIdx.x];
     const SampleDev d = samples[code >> 1];
     const int r = code & 1;
-    const size_t N = (size_t)d.L * d.L * d.L;
+    const int L = d.L, L2 = L * L, N = L2 * L, HALF = N / 2;
     const size_t sbase = (size_t)d.spin_off + (size_t)r * d.n_T * N;
     const int gi = 2 * d.slot_off + r * d.n_T;
-    for (int t = 0; t < d.n_T; ++t) block_copy(frame + sbase + t * N, spins + sbase + (size_t)was[gi + t] * N, N);
+    uint32_t *dst = frame + d.frame_off + (size_t)r * d.n_T * L2;
+    for (int i = threadIdx.x; i < d.n_T * L2; i += blockDim.x) {
+        const int t = i / L2, row = i - t * L2;
+        const int8_t *Sw = spins + sbase + (size_t)was[gi + t] * N;
+        const int yz = (row % L) + row / L;
+        uint32_t bits = 0;
+        for (int x = 0; x < L; ++x) {
+            const int p = (x + yz) & 1;
+            bits |= (uint32_t)(Sw[p * HALF + ((x + L * row) >> 1)] < 0) << x;
+        }
+        dst[i] = bits;
+    }
     const double unit = jkind == 0 ? 0x1p-18 : 1.0;
     for (int t = threadIdx.x; t < d.n_T; t += blockDim.x) {
         const int w = was[gi + t];

@@ -14,9 +14,10 @@
 //           per walker), flips int64 and swaps int64 (per slot / pair)
 //   per (sample, slot), index slot_off + t: beta float64, beta32 float32,
 //           acc float64[36], lut uint32[2][7] (+-1 couplings)
-//   frames  int8   snapshot frames of both chains in slot order, one frame per
-//                  measurement in a chunk: frame f, sample s at
-//                  f*frame_bytes + spin_off[s], layout [2][n_T][2][N/2]
+//   frames  uint32 snapshot frames of both chains in slot order, one frame per
+//                  measurement in a chunk, one bit per spin: frame f, sample s
+//                  at word f*frame_words + frame_off[s], layout [2][n_T][L*L]
+//                  rows, row (y, z) at index y + L z, bit x set iff s = -1
 //   frameE  float64 [frame][2*total_slots] energies of the snapshotted walkers
 #pragma once
 
@@ -28,8 +29,9 @@ namespace ea {
 constexpr int NACC = 36;
 constexpr int NPLANE = 9;
 constexpr int MAX_T = 64;     // temperature slots per sample
-constexpr int MAX_L = 64;
+constexpr int MAX_L = 32;     // a row of spins fits one 32-bit snapshot word
 constexpr int LDS_MAX_L = 16; // largest lattice of the LDS-resident tier
+constexpr int ROW_MAX_THREADS = 768;  // row engine: one thread per (walker, column)
 
 struct SampleDev {
     int32_t L;
@@ -40,6 +42,9 @@ struct SampleDev {
     int64_t J_off;      // elements into Jsub
     int32_t slot_off;   // sum of n_T over earlier samples
     int32_t tier;       // 0 = LDS-resident, 1 = HBM-resident
+    int64_t frame_off;  // words into each snapshot frame
+    uint32_t down_mask; // +-1 couplings: bit a*7+b set iff 2 s (S_J + h) <= 0, s = 2a-1, S_J = 2b-6
+    int32_t pad;
 };
 
 struct SweepArgs {
@@ -57,23 +62,33 @@ struct SweepArgs {
     int32_t *M;
     int64_t *flips;
     int64_t *swaps;
-    int8_t *frames;
+    uint32_t *frames;
     double *frameE;
-    int64_t frame_bytes;
+    int64_t frame_words;
     int64_t total_slots;
     const int64_t *state;       // [0] sweeps completed before this launch
     uint32_t key0, key1;
     int32_t measure_every;
     int32_t pad;
     int64_t measure_start;
+    // HBM-resident tier (one launch per half-sweep / exchange / snapshot)
+    const int32_t *walkers;     // (sample << 7) | (chain << 6) | walker-or-slot
+    int32_t n_walkers;
+    int32_t p;                  // parity of this half-sweep
+    int32_t it;                 // sweep index within the chunk: n = state[0] + it
+    int32_t jkind;              // 0 Gaussian (energy unit 2^-18), 1 +-1 (unit 1)
+    int64_t *dEJ;               // per walker: coupling-energy change of this sweep
+    int32_t *dM;                // per walker: magnetisation change of this sweep
+    int32_t *sow;               // per walker: its slot during this sweep
+    const int32_t *Ju;          // Gaussian couplings as int32 multiples of 2^-18, Jsub layout
 };
 
 struct MeasureArgs {
     const SampleDev *samples;
     const int32_t *slot_sample;  // global slot -> sample
-    const int8_t *frames;
+    const uint32_t *frames;
     const double *frameE;
-    int64_t frame_bytes;
+    int64_t frame_words;
     int64_t total_slots;
     double *acc;
     const double *costab;        // [MAX_L + 1][MAX_L]: cos(2 pi c / L)

@@ -40,7 +40,7 @@ def _desc(work, **over):
     p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
     d = binding.Desc(len(arrs["L"]), p(arrs["sid"]), p(arrs["L"]), p(arrs["nT"]), p(arrs["beta"]),
                      p(arrs["h"]), int(over.get("jkind", work.jkind)), p(arrs["J"]), p(arrs["spins"]),
-                     1, int(over.get("m", 10)), int(over.get("start", 0)))
+                     1, int(over.get("m", 10)), int(over.get("start", 0)), 0)
     return d, arrs
 
 
@@ -107,7 +107,7 @@ def test_rejects_bad_beta(small):
 def test_rejects_bad_sizes(small):
     d, keep = _desc(small, nT=np.array([3, 0], dtype=np.int32))
     assert _create(d)[0] == -1
-    d, keep = _desc(small, L=np.array([4, 66], dtype=np.int32))
+    d, keep = _desc(small, L=np.array([4, 34], dtype=np.int32))
     assert _create(d)[0] == -1
     d, keep = _desc(small, m=-1)
     assert _create(d)[0] == -1

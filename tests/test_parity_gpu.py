@@ -27,9 +27,9 @@ def torch_cuda():
     return torch
 
 
-def gpu_run(work, sweeps, stream=None, plan=None, splits=None, unbatched=False):
+def gpu_run(work, sweeps, stream=None, plan=None, splits=None, unbatched=False, tier=0):
     from paper_1403_4560_amd import binding
-    with binding.Ensemble(work, stream=stream) as ens:
+    with binding.Ensemble(work, stream=stream, tier=tier) as ens:
         if plan:
             ens.set_plan(**plan)
         parts = splits or [sweeps]
@@ -220,3 +220,72 @@ def test_invalid_plan_rejected(torch_cuda):
             ens.set_plan(chunk=0)
         with pytest.raises(binding.EAError):
             ens.sweep_pt(-1)
+
+
+def test_fast_exponential_bracket_is_exhaustively_safe(torch_cuda):
+    from paper_1403_4560_amd import binding
+    v, dev = binding.verify_exp_bracket()
+    print("bracket: violations=%d max relative deviation=%.3g" % (v, dev), flush=True)
+    assert v == 0
+    assert dev < 2.0 ** -17
+
+
+def test_autotune_keeps_results(torch_cuda):
+    from paper_1403_4560_amd import binding
+    work = W.config_workload("mixed_L6_12", samples=[0, 1, 2, 3], measure_start=0)
+    with binding.Ensemble(work) as ens:
+        ens.sweep_pt(7)
+        plan = ens.autotune(trial_sweeps=3)
+        assert plan.threads in (256, 512, 1024)
+        ens.sweep_pt(13)
+        st = ens.read_state()
+        ms = ens.measure()
+    ref = O.OracleEnsemble(work).run(20)
+    assert_same(work, st, ms, ref)
+
+
+# --- HBM-resident tier --------------------------------------------------------
+def test_hbm_L32_pm1_subset(torch_cuda):
+    work = W.config_workload("L32_pm1", samples=[0, 511], measure_start=0, measure_every=5)
+    check(work, 16)
+
+
+def test_hbm_forced_gaussian_L8_L16(torch_cuda):
+    work = W.make_workload([8, 16, 8], [16, 6, 3], (0.5, 2.0), [0.2, 0.1, 0.3], measure_every=4,
+                           measure_start=3, name="forced-hbm")
+    check(work, 30, tier=1)
+
+
+def test_hbm_L24_gaussian_and_mixed_tiers(torch_cuda):
+    work = W.make_workload([24, 4, 8], [4, 5, 6], (0.5, 2.0), [0.2, 0.1, 0.3], measure_every=3,
+                           measure_start=2, name="L24+lds")
+    check(work, 14, plan=dict(chunk=5))
+
+
+def test_hbm_mixed_tiers_pm1(torch_cuda):
+    work = W.make_workload([32, 4, 8, 16], [3, 4, 5, 6], (0.5, 2.0), 0.4, jkind=W.J_PM1, measure_every=2,
+                           measure_start=0, name="pm1 L32+lds")
+    check(work, 12, splits=[5, 7], plan=dict(chunk=4))
+
+
+def test_hbm_unbatched_equals_oracle(torch_cuda):
+    work = W.make_workload([32, 32], 4, (0.5, 2.0), 0.4, jkind=W.J_PM1, sample_ids=[5, 6], measure_every=3,
+                           measure_start=0, name="pm1 unbatched")
+    check(work, 9, unbatched=True)
+
+
+def test_full_L32_workload_sampled(torch_cuda):
+    """The 512-sample, 32-temperature L = 32 batch with +-1 couplings."""
+    from paper_1403_4560_amd import binding
+    work = W.config_workload("L32_pm1", measure_start=0)
+    sweeps = 10
+    print("case: full L32 batch, 512 samples, %d sweeps" % sweeps, flush=True)
+    with binding.Ensemble(work) as ens:
+        ens.set_plan(chunk=10)
+        ens.sweep_pt(sweeps)
+        st = ens.read_state()
+        ms = ens.measure()
+        assert ens.check_energies() == 0
+    pick = [0, 300]
+    ref = O.OracleEnsemble(work.subset(pick)).run(sweeps)
+    assert_same(work, st, ms, ref, samples=pick)
