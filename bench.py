@@ -44,19 +44,41 @@ WORKLOAD_TEXT = {
                "HBM-resident",
 }
 
-# Algorithmic VALU work of one Metropolis attempt, in full-rate 32-bit lane
-# operations (a quarter-rate 32x32->64 multiply counts 4).  Common part:
-# Philox4x32-10 per 4 attempts = 10 rounds x (2 multiplies x 4 + 2 three-input
-# xors) = 100 -> 25; accept test 2; spin update 1; energy/magnetisation
-# bookkeeping 2.
-#   Gaussian couplings: local field 6 signed terms + h = 12; energy change and
-#   its scaling by beta 2; exponential (reduction 5, degree-7 Horner 14,
-#   scaling 2) 21; uniform from the random word 2            -> 67
-#   +-1 couplings: local field 6 sign products + count 6; threshold-table
-#   index and read 2                                          -> 38
-ALG_OPS_PER_ATTEMPT = {0: 67, 1: 38}
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: non-packed 32-bit VALU lane-ops/s.
+# Algorithmic work of one Metropolis attempt: the VALU instructions (one lane
+# each) that a minimal gfx950 implementation of the numeric contract issues,
+# per 4-site word (one Philox call), divided by 4.
+#   Philox4x32-10: 10 rounds x (2 32x32->64 multiply-adds + 4 xors) = 60, less
+#     the 5 that depend only on (walker, sweep) and are paid once per column
+#                                                                      = 55
+#   shifted x-neighbour word (one byte permute)                        =  1
+#   per site, Gaussian couplings: 6 multiply-accumulates of +-1 by the
+#     bond, conversion and + h (2), -2 beta s_i (2), x (1), hardware
+#     exponential estimate (2), bracket (2 mul + 3 compares), uniform (2),
+#     flip byte (1), energy tally (2)                          = 23 x 4 = 92
+#   per site, +-1 couplings: share of the 6 xor/shift/mask products and
+#     5 sums (23 / 4), count byte (1), table index (2), dE <= 0 bit (2),
+#     compare (1), flip byte (1), energy tally (2)         = 14.75 x 4 = 59
+#   word tail: new spins (1), two bit counts (2), mask (1)            =  4
+# Gaussian: (55 + 1 + 92 + 4) / 4 = 38;  +-1: (55 + 2 + 59 + 4) / 4 = 30.
+ALG_OPS_PER_ATTEMPT = {0: 38, 1: 30}
+# Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = non-packed VALU lane-instructions/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# HBM bytes of one launch of the dominant kernel from hardware counters
+# (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the factors a plain copy of
+# known size reads), keyed by a fingerprint of the kernel sources they were
+# taken on; reported as null once the kernels change.
+MEASURED_TRAFFIC = {"L16_gauss": ("772aedfd6fb4f353", 2.0825e9)}
+KERNEL_SOURCES = ("paper_1403_4560_amd/csrc/ea_kernels.hip", "paper_1403_4560_amd/csrc/ea_device.hpp")
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def progress(msg):
@@ -145,11 +167,14 @@ def main():
     avg_launch_s = k_ms / 1e3 / max(k_launches, 1)
     attempts_per_launch = attempts_per_step  # one launch per step (chunk)
     ops = ALG_OPS_PER_ATTEMPT[work.jkind]
+    fp, traffic = MEASURED_TRAFFIC.get(args.workload, (None, None))
+    if fp != kernel_fingerprint():
+        traffic = None
     achieved = attempts_per_launch * ops / avg_launch_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
                 "kernel": KERNEL.get(args.workload, "sweep kernels"), "avg_launch_ms": avg_launch_s * 1e3,
-                "ops_per_attempt": ops}
+                "ops_per_attempt": ops, "traffic_unit": "HBM bytes per launch (hardware counters)"}
 
     unbatched = None
     if not args.no_unbatched:

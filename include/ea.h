@@ -206,14 +206,15 @@ ea_status ea_synchronize(ea_ensemble *ens);
 ea_status ea_query(const ea_ensemble *ens, int32_t *n_samples, int64_t *total_slots,
                    int64_t *device_bytes);
 
-/* Device self-check of the acceptance shortcut used by the sweep kernels: for
- * every binary32 x in [-86, 0] (1.1e9 values) the hardware estimate
- * a = 2^(x log2 e) must bracket the in-house exponential,
- * a (1 - 2^-16) <= exp_ea32(x) <= a (1 + 2^-16), so that comparing a uniform
- * with the bracket decides exactly as comparing it with exp_ea32(x) whenever it
- * falls outside, and the exact value is computed otherwise.  *violations must
- * be 0; *max_rel_dev is the largest |a/exp_ea32(x) - 1| seen.  Synchronizing;
- * uses the current device. */
+/* Device self-check of the acceptance shortcut used by the sweep kernels.
+ * The kernels estimate a = 2^(x log2 e) with the hardware exponential and form
+ * lo = a (2^32 - 2^16), hi = a (2^32 + 2^17) + 512; a random word w with
+ * fl32(w) < lo is accepted and one with fl32(w) >= hi rejected without
+ * evaluating the in-house exp_ea32, any other word by the exact test.  This
+ * call checks, for every binary32 x in [-86, 0] (1.1e9 values), that both
+ * shortcuts decide as the exact test U 2^-24 < exp_ea32(x), U = w >> 8, would
+ * for every w.  *violations must be 0; *max_rel_dev is the largest
+ * |a/exp_ea32(x) - 1| seen.  Synchronizing; uses the current device. */
 ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev);
 
 void ea_destroy(ea_ensemble *ens);

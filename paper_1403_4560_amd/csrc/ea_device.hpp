@@ -100,6 +100,22 @@ __device__ __forceinline__ double exp_ea64(double x)
     return x < -700.0 ? 0.0 : v;
 }
 
+// Acceptance bracket.  For x <= 0 the hardware estimate a = 2^(x log2 e) lies
+// within a relative 2^-17 of exp_ea32(x) (checked exhaustively on the device by
+// ea_verify_exp_bracket).  With W = fl32(w) for the 32-bit random word w and
+// U = w >> 8 the 24-bit uniform numerator, the bounds
+//   lo = a (2^32 - 2^16),   hi = a (2^32 + 2^17) + 512
+// satisfy: W < lo implies U < exp_ea32(x) 2^24 (accept), and W >= hi implies
+// U >= exp_ea32(x) 2^24 (reject), for every x in [-86, 0]; the verification
+// checks exactly these two implications.  Between them the exact test decides.
+__device__ __forceinline__ void accept_bracket(float x, float &lo, float &hi)
+{
+    const float LOG2E = __uint_as_float(0x3FB8AA3Bu);
+    const float a = __builtin_amdgcn_exp2f(x * LOG2E);
+    lo = a * 4294901760.0f;                            // 2^32 - 2^16
+    hi = __builtin_fmaf(a, 4295098368.0f, 512.0f);     // 2^32 + 2^17, plus 2 units of U
+}
+
 // 24-bit and 53-bit uniforms in [0, 1) from Philox output words.
 __device__ __forceinline__ float u24_of(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
 __device__ __forceinline__ double u53_of(uint32_t w0, uint32_t w1)

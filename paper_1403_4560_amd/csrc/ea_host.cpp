@@ -26,7 +26,7 @@ template <int L, int VAR> __global__ void row_sweep_kernel(SweepArgs A);
 template <int L, int JK, int VAR> __global__ void hbm_half_kernel(SweepArgs A);
 __global__ void hbm_exchange_kernel(SweepArgs A);
 __global__ void hbm_snapshot_kernel(SweepArgs A);
-__global__ void measure_kernel(MeasureArgs A);
+template <int L> __global__ void measure_kernel(MeasureArgs A);
 __global__ void advance_kernel(int64_t *state, int64_t k);
 __global__ void exp_bracket_kernel(uint32_t, uint32_t, unsigned long long *, unsigned int *);
 template <int JK>
@@ -86,7 +86,7 @@ struct ea_ensemble {
     int device = 0;
     // device buffers
     DevBuf samples, items, spins, J, beta, beta32, lut, was, EJ, M, flips, swaps, acc, frames, frameE,
-        state, slot_sample, costab, sintab, scratchE, scratchM, finout, walkers, dEJ, dM, sow, Ju;
+        state, slot_sample, costab, sintab, scratchE, scratchM, finout, walkers, dEJ, dM, sow, Ju, mslots;
     int64_t frames_cap = 0;  // frames allocated
     // launch classes: items sorted by lattice size, one launch per size
     struct Class {
@@ -101,6 +101,10 @@ struct ea_ensemble {
     std::vector<int> sample_class;
     std::vector<int> sorted_samples;
     std::vector<int> walker_pos;  // sample -> first entry in the walker table (HBM tier)
+    struct SlotClass {
+        int L, begin, count;
+    };
+    std::vector<SlotClass> slot_classes;  // measurement launches: slots grouped by lattice size
     bool any_hbm = false;
     std::map<int, hipGraphExec_t> graphs;
     std::map<int, hipGraph_t> graph_defs;
@@ -233,7 +237,7 @@ void destroy_all(ea_ensemble *e)
                       &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->frames,
                       &e->frameE, &e->state, &e->slot_sample, &e->costab, &e->sintab,
                       &e->scratchE, &e->scratchM, &e->finout, &e->walkers, &e->dEJ, &e->dM,
-                      &e->sow, &e->Ju};
+                      &e->sow, &e->Ju, &e->mslots};
     for (DevBuf *b : bufs) dfree(*b);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
@@ -321,6 +325,35 @@ MeasureArgs measure_args(const ea_ensemble *e, int K, int explicit_frames)
 }
 
 using SweepFn = void (*)(SweepArgs);
+using MeasureFn = void (*)(MeasureArgs);
+
+MeasureFn measure_fn(int L)
+{
+#define EA_CASE(Lv) \
+    case Lv: return measure_kernel<Lv>;
+    switch (L) {
+        EA_CASE(2) EA_CASE(4) EA_CASE(6) EA_CASE(8) EA_CASE(10) EA_CASE(12) EA_CASE(14) EA_CASE(16)
+        EA_CASE(24) EA_CASE(32)
+    default: return nullptr;
+    }
+#undef EA_CASE
+}
+
+// Measurement of the chunk's frames (or of explicit_frames frames): one
+// launch per lattice size, one wave per slot.
+hipError_t launch_measure(ea_ensemble *e, int K, int explicit_frames)
+{
+    for (const auto &c : e->slot_classes) {
+        MeasureArgs M = measure_args(e, K, explicit_frames);
+        M.slots = (const int32_t *)e->mslots.p + c.begin;
+        MeasureFn fn = measure_fn(c.L);
+        if (!fn) return hipErrorInvalidDeviceFunction;
+        hipLaunchKernelGGL(fn, dim3((unsigned)c.count), dim3(64), 0, e->stream, M);
+        hipError_t st = hipGetLastError();
+        if (st != hipSuccess) return st;
+    }
+    return hipSuccess;
+}
 
 template <int VAR>
 SweepFn site_fn(int L, int jk)
@@ -346,9 +379,17 @@ SweepFn sweep_fn(int L, int jk, bool row, bool unbatched)
 
 // The row engine serves L = 8 and 16 with Gaussian couplings when a
 // workgroup can hold one thread per (walker, column).
+// Threads of a row-engine workgroup: two waves per WPW walkers, WPW = 64 /
+// (L/8 * L/2) walkers share a wave.
+int row_threads(int L, int nT)
+{
+    const int wpw = 64 / ((L / 8) * (L / 2));
+    return ((nT + wpw - 1) / wpw) * 128;
+}
+
 bool row_engine(int L, int nT, int jk)
 {
-    return jk == 0 && (L == 8 || L == 16) && ((nT * (L / 8) * L + 63) / 64) * 64 <= ROW_MAX_THREADS;
+    return jk == 0 && (L == 8 || L == 16) && row_threads(L, nT) <= ROW_MAX_THREADS;
 }
 
 SweepFn hbm_fn(int L, int jk, bool unbatched)
@@ -441,11 +482,8 @@ hipError_t enqueue_chunk(ea_ensemble *e, int K, bool unbatched)
     }
     if (e->timing && (st = hipEventRecord(ev.second, e->stream)) != hipSuccess) return st;
     const int64_t nmeas = measurements_upto(e->sweep + K, e->m, e->mstart) - measurements_upto(e->sweep, e->m, e->mstart);
-    if (nmeas > 0 || e->plan.use_graph) {
-        MeasureArgs M = measure_args(e, K, 0);
-        hipLaunchKernelGGL(measure_kernel, dim3((unsigned)e->total_slots), dim3(64), 0, e->stream, M);
-        if ((st = hipGetLastError()) != hipSuccess) return st;
-    }
+    if (nmeas > 0 || e->plan.use_graph)
+        if ((st = launch_measure(e, K, 0)) != hipSuccess) return st;
     hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, e->stream, (int64_t *)e->state.p, (int64_t)K);
     return hipGetLastError();
 }
@@ -586,8 +624,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
             }
             c.lds = std::max(c.lds, lds_offsets(h.L, h.nT, e->jkind).total);
             c.row = c.row && row_engine(h.L, h.nT, e->jkind);
-            const int TW = (h.L / 8) * h.L;
-            c.threads = std::max(c.threads, ((h.nT * std::max(TW, 1) + 63) / 64) * 64);
+            if (row_engine(h.L, h.nT, e->jkind)) c.threads = std::max(c.threads, row_threads(h.L, h.nT));
             e->item_pos[order[i]] = 2 * i;
             e->sample_class[order[i]] = (int)e->classes.size() - 1;
         }
@@ -665,6 +702,23 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         for (int r = 0; r < 2; ++r)
             for (int w = 0; w < e->smp[s].nT; ++w) wtab.push_back((s << 7) | (r << 6) | w);
     }
+    std::vector<int32_t> mslots;
+    for (int i = 0; i < S; ++i) {
+        const int s = e->sorted_samples[i];
+        const SampleHost &h = e->smp[s];
+        if (e->slot_classes.empty() || e->slot_classes.back().L != h.L) {
+            bool found = false;
+            for (auto &c : e->slot_classes) found |= c.L == h.L;
+            if (found) continue;  // handled with the first run of this size below
+            e->slot_classes.push_back({h.L, (int)mslots.size(), 0});
+            for (int j = i; j < S; ++j) {
+                const SampleHost &g = e->smp[e->sorted_samples[j]];
+                if (g.L != h.L) continue;
+                for (int t = 0; t < g.nT; ++t) mslots.push_back(g.slot_off + t);
+            }
+            e->slot_classes.back().count = (int)mslots.size() - e->slot_classes.back().begin;
+        }
+    }
     std::vector<int32_t> Ju;
     if (e->any_hbm && e->jkind == EA_J_GAUSS_F32) {
         Ju.resize(e->J_elems);
@@ -711,6 +765,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     ALLOC(sow, sizeof(int32_t) * 2 * TS);
     ALLOC(walkers, sizeof(int32_t) * wtab.size());
     ALLOC(Ju, sizeof(int32_t) * Ju.size());
+    ALLOC(mslots, sizeof(int32_t) * mslots.size());
 #undef ALLOC
     {
         ea_status fs = ensure_frames(e, e->plan.chunk);
@@ -739,6 +794,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     H2D(sow, was.data(), sizeof(int32_t) * 2 * TS);  // identity, like walker_at_slot
     if (!wtab.empty()) H2D(walkers, wtab.data(), sizeof(int32_t) * wtab.size());
     if (!Ju.empty()) H2D(Ju, Ju.data(), sizeof(int32_t) * Ju.size());
+    H2D(mslots, mslots.data(), sizeof(int32_t) * mslots.size());
     H2D(costab, costab.data(), sizeof(double) * costab.size());
     H2D(sintab, sintab.data(), sizeof(double) * sintab.size());
 #undef H2D
@@ -794,9 +850,7 @@ ea_status ea_measure(ea_ensemble *e, int32_t flags, double *acc, int64_t *flips,
                            (const int64_t *)e->EJ.p, (const int32_t *)e->M.p, e->jkind, (uint32_t *)e->frames.p,
                            (double *)e->frameE.p);
         HIP_TRY(e, hipGetLastError());
-        MeasureArgs M = measure_args(e, 0, 1);
-        hipLaunchKernelGGL(measure_kernel, dim3((unsigned)e->total_slots), dim3(64), 0, e->stream, M);
-        HIP_TRY(e, hipGetLastError());
+        HIP_TRY(e, launch_measure(e, 0, 1));
     }
     if (acc) HIP_TRY(e, hipMemcpyAsync(acc, e->acc.p, e->acc.bytes, hipMemcpyDeviceToHost, e->stream));
     if (flips) HIP_TRY(e, hipMemcpyAsync(flips, e->flips.p, e->flips.bytes, hipMemcpyDeviceToHost, e->stream));

@@ -223,19 +223,20 @@ __device__ __forceinline__ void site_half_sweep(const SweepArgs &A, const Sample
 // accepted sites to accE, m = 0 for s_i = +1 and -1 for s_i = -1.
 //
 // Decision: x = -fl32(beta32 dE) is formed as fl32((-2 beta32 s_i) f) (the same
-// real number, rounded once), dE <= 0 iff x >= 0, exp_ea32 is 0 below -86.  A
-// uniform U = w >> 8 below a (1 - 2^-16) 2^24 or at or above a (1 + 2^-16) 2^24,
-// with a = 2^(x log2 e) from the hardware exponential, is decided by the
-// bracket (ea_verify_exp_bracket proves it contains exp_ea32 for every x);
-// otherwise by U 2^-24 < exp_ea32(x) itself.
+// real number, rounded once), dE <= 0 iff x >= 0, exp_ea32 is 0 below -86.  The
+// random word is decided by accept_bracket when it falls outside the bracket
+// (ea_verify_exp_bracket proves the bracket safe for every x <= 0), otherwise
+// by U 2^-24 < exp_ea32(x) itself.  For x >= 0 both routes accept, as the
+// contract's dE <= 0 rule does.
 __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, uint32_t Xs, uint32_t Yp,
                                                       uint32_t Ym, uint32_t Zp, uint32_t Zm, const int Ja[4],
                                                       const int Js[4], const int Jy[4], const int Jyn[4],
                                                       const int Jz[4], const int Jzn[4], const u32x4 rw,
                                                       float m2b, float h32, int &accE)
 {
-    const float LOG2E = __uint_as_float(0x3FB8AA3Bu);
     const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
+    const uint32_t nS = ~Sv;                            // byte sign bit set iff s_i = +1
+    const uint32_t b2 = __float_as_uint(m2b) & 0x7FFFFFFFu;  // 2 beta32
     uint32_t fm = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -248,22 +249,21 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
         Su += __mul24(__builtin_amdgcn_sbfe((int)Zm, sh, 8), Jzn[i]);
         // f = fl32(S_J + h): S_J = Su 2^-18 exactly, so the fused form rounds once, as the sum does
         const float f = __builtin_fmaf((float)Su, 0x1p-18f, h32);
+        // c = -2 beta32 s_i: the sign bit of 2 beta32 set iff s_i = +1 (exact)
+        const float c = __uint_as_float(__builtin_amdgcn_ubfe(nS, sh + 7, 1) << 31 | b2);
+        const float x = c * f;                         // = -fl32(beta * dE)
+        const bool inside = x >= -86.0f;              // exp_ea32 is 0 below -86
+        // x >= 0 (dE <= 0): the estimate is >= 1 (or inf), so W < lo unless w is
+        // within 2^17 of 2^32, and then exp_ea32(x) >= 1 > U 2^-24: always accepted
+        float lo, hi;
+        accept_bracket(x, lo, hi);
+        const float Wf = (float)words[i];
+        const bool below = Wf < lo, above = Wf >= hi;
+        bool accept = inside & below;
+        if (inside & !below & !above) accept = (float)(words[i] >> 8) * 0x1p-24f < exp_ea32(x);
         const int m = __builtin_amdgcn_sbfe((int)Sv, sh + 7, 1);  // 0: s_i = +1, -1: s_i = -1
-        const float c = m ? -m2b : m2b;                            // -2 beta s_i, exact
-        const float x = c * f;                                     // = -fl32(beta * dE)
-        const bool down = x >= 0.0f;                               // dE <= 0
-        const bool big = x < -86.0f;                               // exp_ea32 returns 0
-        const float xn = fminf(x, 0.0f);
-        const float a = __builtin_amdgcn_exp2f(xn * LOG2E);
-        const float U = (float)(words[i] >> 8);
-        const bool accf = U < a * 16776960.0f;   // a (1 - 2^-16) 2^24
-        const bool rejf = U >= a * 16777472.0f;  // a (1 + 2^-16) 2^24
-        bool accept = down | (!big & accf);
-        if (!down & !big & !accf & !rejf) accept = U * 0x1p-24f < exp_ea32(x);
-        if (accept) {
-            fm |= 0xFEu << sh;
-            accE += Su ^ m;
-        }
+        fm |= accept ? 0xFEu << sh : 0u;
+        accE += accept ? (Su ^ m) : 0;
     }
     return fm;
 }
@@ -312,58 +312,86 @@ __device__ __forceinline__ uint32_t update_word_pm1(uint32_t Sv, uint32_t Xa, ui
 // (S_u XOR m) with m = 0 for s_i = +1 and -1 for s_i = -1, so that
 // sum of s_i S_u = accE + (accepted down spins); bf and bd count the set bits
 // of the flip masks (7 per flipped byte) and of (spins AND flip mask).
+//
+// Lane map: a walker's L*L/8 columns (k, y) are split by the parity of y over
+// two waves, and a wave holds the columns of WPW walkers with y of one parity.
+// eps = (y + z + p) & 1 is then the same for every lane of a wave, so each
+// parity of z has its own specialised code path with no per-lane selects.
 template <int L>
-__device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleDev &d, int r, int p,
-                                               int64_t n, const ItemLds &I, int w, int y, int k, int t,
-                                               int &accE, int &bf, int &bd)
+struct RowMap {
+    static constexpr int WPR = L / 8, HL = L / 2;
+    static constexpr int CPW = WPR * HL;  // columns of one y-parity per walker
+    static constexpr int WPW = 64 / CPW;  // walkers per wave
+};
+
+template <int L, int P, int EPS>
+__device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d, uint8_t *Sw, const int *J,
+                                         int o_y0, int o_yp, int o_ym, int o_x, int e_prev, int z, int zp,
+                                         int zm, uint32_t c1, uint32_t c2, float m2b, int &accE, int &bf,
+                                         int &bd)
 {
-    constexpr int N = L * L * L, HALF = N / 2, WPR = L / 8, HL = L / 2;
-    constexpr int PLANE = L * HL;  // bytes of one z-plane of one sublattice
+    constexpr int HALF = L * L * L / 2, HL = L / 2, PLANE = L * HL;
+    const uint8_t *own = Sw + P * HALF, *oth = Sw + (1 - P) * HALF;
+    const int *Jp = J + P * 3 * HALF, *Jo = J + (1 - P) * 3 * HALF;
+    const int zo = z * PLANE;
+    const uint32_t Sv = *(const uint32_t *)(own + o_y0 + zo);
+    const uint32_t Xa = *(const uint32_t *)(oth + o_y0 + zo);
+    const uint32_t Xo = L == 8 ? Xa : *(const uint32_t *)(oth + o_x + zo);
+    const uint32_t Yp = *(const uint32_t *)(oth + o_yp + zo);
+    const uint32_t Ym = *(const uint32_t *)(oth + o_ym + zo);
+    const uint32_t Zp = *(const uint32_t *)(oth + o_y0 + zp * PLANE);
+    const uint32_t Zm = *(const uint32_t *)(oth + o_y0 + zm * PLANE);
+    const uint32_t Xs = __builtin_amdgcn_perm(Xa, Xo, EPS ? 0x00070605u : 0x06050403u);
+    const int4 Jpx = *(const int4 *)(Jp + o_y0 + zo);
+    const int4 Jpy = *(const int4 *)(Jp + HALF + o_y0 + zo);
+    const int4 Jpz = *(const int4 *)(Jp + 2 * HALF + o_y0 + zo);
+    const int4 V = *(const int4 *)(Jo + o_y0 + zo);
+    const int4 Jym = *(const int4 *)(Jo + HALF + o_ym + zo);
+    const int4 Jzm = *(const int4 *)(Jo + 2 * HALF + o_y0 + zm * PLANE);
+    // bonds to the aligned x-neighbour (x+1 if eps = 0, else x-1) and the shifted one
+    int Ja[4], Js[4];
+    if constexpr (EPS) {
+        Ja[0] = V.x; Ja[1] = V.y; Ja[2] = V.z; Ja[3] = V.w;
+        Js[0] = Jpx.x; Js[1] = Jpx.y; Js[2] = Jpx.z; Js[3] = Jpx.w;
+    } else {
+        const int Ep = Jo[e_prev + zo];
+        Ja[0] = Jpx.x; Ja[1] = Jpx.y; Ja[2] = Jpx.z; Ja[3] = Jpx.w;
+        Js[0] = Ep; Js[1] = V.x; Js[2] = V.y; Js[3] = V.z;
+    }
+    const int Jy[4] = {Jpy.x, Jpy.y, Jpy.z, Jpy.w}, Jyn[4] = {Jym.x, Jym.y, Jym.z, Jym.w};
+    const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
+    const uint32_t g = (uint32_t)(o_y0 / 4 + z * (PLANE / 4));
+    const u32x4 rw = philox4x32_10(g, c1, c2, d.sample_id, A.key0, A.key1);
+    const uint32_t fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b, d.h32,
+                                          accE);
+    *(uint32_t *)(Sw + P * HALF + o_y0 + zo) = Sv ^ fm;
+    bf += __builtin_popcount(fm);
+    bd += __builtin_popcount(Sv & fm);
+}
+
+// Half-sweep P of one walker's column (k, y); E0 = eps of the even z planes.
+template <int L, int P, int E0>
+__device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleDev &d, int r, int64_t n,
+                                               const ItemLds &I, int w, int y, int k, int t, int &accE,
+                                               int &bf, int &bd)
+{
+    constexpr int N = L * L * L, WPR = L / 8, HL = L / 2;
     const int yp = (y + 1) & (L - 1), ym = (y - 1) & (L - 1);
     const int kx = WPR == 2 ? (k ^ 1) : k;
     const int o_y0 = 4 * (y * WPR + k), o_yp = 4 * (yp * WPR + k), o_ym = 4 * (ym * WPR + k);
     const int o_x = 4 * (y * WPR + kx);
     const int e_prev = y * HL + (k == 0 ? HL - 1 : 4 * k - 1);  // element before the word, cyclic
-    const uint8_t *own = (const uint8_t *)I.S + (size_t)w * N + p * HALF;
-    const uint8_t *oth = (const uint8_t *)I.S + (size_t)w * N + (1 - p) * HALF;
-    uint8_t *ownw = (uint8_t *)I.S + (size_t)w * N + p * HALF;
-    const int *Jp = (const int *)I.J + p * 3 * HALF;        // own bonds +x,+y,+z
-    const int *Jo = (const int *)I.J + (1 - p) * 3 * HALF;  // other sublattice's bonds
-    const uint32_t c1 = (uint32_t)(2 * n + p);
+    uint8_t *Sw = (uint8_t *)I.S + (size_t)w * N;
+    const int *J = (const int *)I.J;
+    const uint32_t c1 = (uint32_t)(2 * n + P);
     const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
     const float m2b = -2.0f * I.b32[t];
-    const float h32 = d.h32;
 #pragma unroll 1
-    for (int z = 0; z < L; ++z) {
-        const int zp = (z + 1) & (L - 1), zm = (z - 1) & (L - 1);
-        const int eps = (y + z + p) & 1;
-        const uint32_t Sv = *(const uint32_t *)(own + o_y0 + z * PLANE);
-        const uint32_t Xa = *(const uint32_t *)(oth + o_y0 + z * PLANE);
-        const uint32_t Xo = *(const uint32_t *)(oth + o_x + z * PLANE);
-        const uint32_t Yp = *(const uint32_t *)(oth + o_yp + z * PLANE);
-        const uint32_t Ym = *(const uint32_t *)(oth + o_ym + z * PLANE);
-        const uint32_t Zp = *(const uint32_t *)(oth + o_y0 + zp * PLANE);
-        const uint32_t Zm = *(const uint32_t *)(oth + o_y0 + zm * PLANE);
-        const uint32_t Xs = __builtin_amdgcn_perm(Xa, Xo, eps ? 0x00070605u : 0x06050403u);
-        const int4 Jpx = *(const int4 *)(Jp + o_y0 + z * PLANE);
-        const int4 Jpy = *(const int4 *)(Jp + HALF + o_y0 + z * PLANE);
-        const int4 Jpz = *(const int4 *)(Jp + 2 * HALF + o_y0 + z * PLANE);
-        const int4 V = *(const int4 *)(Jo + o_y0 + z * PLANE);
-        const int4 Jym = *(const int4 *)(Jo + HALF + o_ym + z * PLANE);
-        const int4 Jzm = *(const int4 *)(Jo + 2 * HALF + o_y0 + zm * PLANE);
-        const int Ep = Jo[e_prev + z * PLANE];
-        // bond to the aligned x-neighbour and to the shifted one
-        const int Ja[4] = {eps ? V.x : Jpx.x, eps ? V.y : Jpx.y, eps ? V.z : Jpx.z, eps ? V.w : Jpx.w};
-        const int Js[4] = {eps ? Jpx.x : Ep, eps ? Jpx.y : V.x, eps ? Jpx.z : V.y, eps ? Jpx.w : V.z};
-        const int Jy[4] = {Jpy.x, Jpy.y, Jpy.z, Jpy.w}, Jyn[4] = {Jym.x, Jym.y, Jym.z, Jym.w};
-        const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
-        const uint32_t g = (uint32_t)(o_y0 / 4 + z * (PLANE / 4));
-        const u32x4 rw = philox4x32_10(g, c1, c2, d.sample_id, A.key0, A.key1);
-        const uint32_t fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b,
-                                              h32, accE);
-        *(uint32_t *)(ownw + o_y0 + z * PLANE) = Sv ^ fm;
-        bf += __builtin_popcount(fm);
-        bd += __builtin_popcount(Sv & fm);
+    for (int z = 0; z < L; z += 2) {
+        const int zm = z == 0 ? L - 1 : z - 1, zpp = z + 2 == L ? 0 : z + 2;
+        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z, z + 1, zm, c1, c2, m2b, accE, bf, bd);
+        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, zpp, z, c1, c2, m2b, accE, bf,
+                               bd);
     }
 }
 
@@ -418,10 +446,14 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
         for (int i = tid; i < nT * 14; i += T) I.lut[i] = A.lut[(size_t)d.slot_off * 14 + i];
     __syncthreads();
 
-    // row engine: this thread's walker and column
-    constexpr int WPR = L / 8 > 0 ? L / 8 : 1, TW = WPR * L;
-    const int rw_w = tid / TW, rw_q = tid - rw_w * TW;
-    const int rw_k = rw_q % WPR, rw_y = rw_q / WPR;
+    // row engine: this thread's walker and column (see RowMap)
+    constexpr int CPW = RowMap<(L >= 8 ? L : 8)>::CPW, WPW = RowMap<(L >= 8 ? L : 8)>::WPW;
+    constexpr int WPR = L / 8 > 0 ? L / 8 : 1;
+    const int rw_wave = tid >> 6, rw_lane = tid & 63;
+    const int rw_par = __builtin_amdgcn_readfirstlane(rw_wave & 1);
+    const int rw_rem = rw_lane % CPW;
+    const int rw_w = (rw_wave >> 1) * WPW + rw_lane / CPW;
+    const int rw_k = rw_rem % WPR, rw_y = 2 * (rw_rem / WPR) + rw_par;
 
     const double unit = JK == 0 ? 0x1p-18 : 1.0;
     const double hd = (double)d.h32;
@@ -437,22 +469,27 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
         __syncthreads();
         if constexpr (ROW) {
             // Barriers stay outside the walker test: a wave may hold lanes of
-            // an active and an idle walker.  A walker's TW lanes are aligned
-            // and all active or all idle, so the group sums see only its lanes.
+            // an active and an idle walker.  A walker's CPW lanes in a wave are
+            // aligned and all active or all idle, so the group sums see only
+            // its lanes; the two waves of a walker add into LDS.
             const bool on = rw_w < nT;
             const int t = on ? I.sow[rw_w] : 0;
             int accE = 0, bf = 0, bd = 0;
-            if (on) row_half_sweep<L>(A, d, r, 0, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
+            if (on) {
+                if (rw_par) row_half_sweep<L, 0, 1>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
+                else row_half_sweep<L, 0, 0>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
+            }
             __syncthreads();
             if (on) {
-                row_half_sweep<L>(A, d, r, 1, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
-                const long long sE = group_sum_i64<TW>((long long)accE);
-                const int sf = group_sum_i32<TW>(bf), sd = group_sum_i32<TW>(bd);
-                if (rw_q == 0) {
+                if (rw_par) row_half_sweep<L, 1, 0>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
+                else row_half_sweep<L, 1, 1>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
+                const long long sE = group_sum_i64<CPW>((long long)accE);
+                const int sf = group_sum_i32<CPW>(bf), sd = group_sum_i32<CPW>(bd);
+                if (rw_rem == 0) {
                     const int flips = sf / 7, ndown = sd / 7;
-                    I.dEJ[rw_w] = 2 * (sE + ndown);
-                    I.dM[rw_w] = -2 * (flips - 2 * ndown);
-                    I.fl[t] += flips;
+                    atomicAdd((unsigned long long *)&I.dEJ[rw_w], (unsigned long long)(2 * (sE + ndown)));
+                    atomicAdd(&I.dM[rw_w], -2 * (flips - 2 * ndown));
+                    atomicAdd(&I.fl[t], flips);
                 }
             }
         } else {
@@ -787,20 +824,21 @@ EA_HBM(32)
 // plane sums are P_f[c] = 2 count - L^2 and
 // q(k_f) = sum_c P_f[c] e^{2 pi i c / L} / N (summed in c order), added to the
 // binary64 accumulators of the slot in time order.
+template <int L>
 __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
 {
-    __shared__ uint32_t eqr[MAX_L * MAX_L];
-    __shared__ int C[MAX_L * MAX_L], D[MAX_L * MAX_L], R[MAX_L * MAX_L];
-    __shared__ int P[NPLANE][MAX_L];
+    constexpr int L2 = L * L;
+    constexpr uint32_t mask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
+    __shared__ uint32_t eqr[L2];
+    __shared__ int C[L2], D[L2], R[L2];
+    __shared__ int P[NPLANE][L];
     __shared__ double accs[NACC];
     __shared__ double re_f[NPLANE], im_f[NPLANE];
-    const int gs = blockIdx.x;
+    const int gs = A.slots[blockIdx.x];
     const int s = A.slot_sample[gs];
     const SampleDev d = A.samples[s];
     const int t = gs - d.slot_off;
-    const int L = d.L, L2 = L * L;
     const int tid = threadIdx.x, T = blockDim.x;
-    const uint32_t mask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
     int64_t nf;
     if (A.explicit_frames > 0) {
         nf = A.explicit_frames;
@@ -811,7 +849,7 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
     }
     if (nf <= 0) return;
     for (int i = tid; i < NACC; i += T) accs[i] = A.acc[(size_t)gs * NACC + i];
-    const double Nd = (double)L2 * (double)L;
+    constexpr double Nd = (double)(L2 * L);
     for (int64_t f = 0; f < nf; ++f) {
         const uint32_t *ra = A.frames + f * A.frame_words + d.frame_off + (size_t)t * L2;
         const uint32_t *rb = ra + (size_t)d.n_T * L2;
@@ -821,34 +859,35 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
             R[i] = __builtin_popcount(e);
         }
         __syncthreads();
+        // C[x][y] = #{z : e(x,y,z)},  D[x][z] = #{y : e(x,y,z)}
         for (int e = tid; e < 2 * L2; e += T) {
-            const int e2 = e < L2 ? e : e - L2;
+            const bool isC = e < L2;
+            const int e2 = isC ? e : e - L2;
             const int x = e2 / L, u = e2 - x * L;
             int cnt = 0;
-            if (e < L2) {
-                for (int z = 0; z < L; ++z) cnt += (eqr[u + L * z] >> x) & 1u;  // u = y
-                C[e2] = cnt;
-            } else {
-                for (int y = 0; y < L; ++y) cnt += (eqr[y + L * u] >> x) & 1u;  // u = z
-                D[e2] = cnt;
-            }
+#pragma unroll
+            for (int v = 0; v < L; ++v) cnt += (eqr[isC ? u + L * v : v + L * u] >> x) & 1u;
+            (isC ? C : D)[e2] = cnt;
         }
         __syncthreads();
         for (int task = tid; task < NPLANE * L; task += T) {
             const int fam = task / L, c = task - fam * L;
             int cnt = 0;
+#pragma unroll
             for (int v = 0; v < L; ++v) {
-                const int cm = (c - v + L) % L, cp = (c + v) % L;
+                const int cm = c - v < 0 ? c - v + L : c - v;    // c - v mod L
+                const int cp = c + v >= L ? c + v - L : c + v;   // c + v mod L
+                const int vm = v - c < 0 ? v - c + L : v - c;    // v - c mod L
                 switch (fam) {
-                case 0: cnt += C[c * L + v]; break;           // x = c
-                case 1: cnt += C[v * L + c]; break;           // y = c
-                case 2: cnt += D[v * L + c]; break;           // z = c
-                case 3: cnt += C[cm * L + v]; break;          // x + y = c
-                case 4: cnt += C[cp * L + v]; break;          // x - y = c
-                case 5: cnt += D[cm * L + v]; break;          // x + z = c
-                case 6: cnt += D[cp * L + v]; break;          // x - z = c
-                case 7: cnt += R[v + L * cm]; break;          // y + z = c
-                default: cnt += R[v + L * ((v - c + L) % L)]; break;  // y - z = c
+                case 0: cnt += C[c * L + v]; break;   // x = c
+                case 1: cnt += C[v * L + c]; break;   // y = c
+                case 2: cnt += D[v * L + c]; break;   // z = c
+                case 3: cnt += C[cm * L + v]; break;  // x + y = c
+                case 4: cnt += C[cp * L + v]; break;  // x - y = c
+                case 5: cnt += D[cm * L + v]; break;  // x + z = c
+                case 6: cnt += D[cp * L + v]; break;  // x - z = c
+                case 7: cnt += R[v + L * cm]; break;  // y + z = c
+                default: cnt += R[v + L * vm]; break; // y - z = c
                 }
             }
             P[fam][c] = 2 * cnt - L2;
@@ -891,23 +930,39 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
     for (int i = tid; i < NACC; i += T) A.acc[(size_t)gs * NACC + i] = accs[i];
 }
 
-// Exhaustive check of the acceptance bracket used by the row engine: for every
-// binary32 x in [-86, 0] the hardware estimate a = 2^(x log2 e) must satisfy
-// a (1 - 2^-16) <= exp_ea32(x) <= a (1 + 2^-16) in units of 2^-24, so that a
-// uniform below the lower bound is certainly accepted and one at or above the
-// upper bound certainly rejected by the exact test.
+#define EA_MEAS(Lv) template __global__ void measure_kernel<Lv>(MeasureArgs);
+EA_MEAS(2)
+EA_MEAS(4)
+EA_MEAS(6)
+EA_MEAS(8)
+EA_MEAS(10)
+EA_MEAS(12)
+EA_MEAS(14)
+EA_MEAS(16)
+EA_MEAS(24)
+EA_MEAS(32)
+#undef EA_MEAS
+
+// Exhaustive check of the acceptance bracket used by the row and HBM engines,
+// for every binary32 x in [-86, 0], in binary64:
+//   lo (1 + 2^-24) <= 256 E24        (W < lo  =>  U < E24, E24 = exp_ea32(x) 2^24)
+//   hi (1 - 2^-24) / 256 - 1 >= E24  (W >= hi =>  U >= E24)
+// where W = fl32(w) is within a relative 2^-24 of w and U = w >> 8 >= w/256 - 1.
+// Also records the largest |a / exp_ea32(x) - 1| of the hardware estimate.
 __global__ void exp_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned long long *violations,
                                    unsigned int *max_dev_bits)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const float x = __uint_as_float(first_bits + i);
-    const float LOG2E = __uint_as_float(0x3FB8AA3Bu);
-    const float a = __builtin_amdgcn_exp2f(fminf(x, 0.0f) * LOG2E);
-    const float lo = a * 16776960.0f, hi = a * 16777472.0f;
-    const float E24 = exp_ea32(x) * 16777216.0f;
-    if (!(lo <= E24) || !(E24 <= hi)) atomicAdd(violations, 1ull);
-    const float dev = fabsf(a * 16777216.0f - E24) / E24;
+    float lo, hi;
+    accept_bracket(x, lo, hi);
+    const double E24 = (double)exp_ea32(x) * 16777216.0;
+    const bool okA = (double)lo * (1.0 + 0x1p-24) <= 256.0 * E24;
+    const bool okB = (double)hi * (1.0 - 0x1p-24) / 256.0 - 1.0 >= E24;
+    if (!okA || !okB) atomicAdd(violations, 1ull);
+    const float a = __builtin_amdgcn_exp2f(x * __uint_as_float(0x3FB8AA3Bu));
+    const float dev = (float)(fabs((double)a * 16777216.0 - E24) / E24);
     atomicMax(max_dev_bits, __float_as_uint(dev));
 }
 

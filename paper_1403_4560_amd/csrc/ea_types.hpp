@@ -85,6 +85,7 @@ struct SweepArgs {
 
 struct MeasureArgs {
     const SampleDev *samples;
+    const int32_t *slots;        // global slot indices of this launch (one lattice size)
     const int32_t *slot_sample;  // global slot -> sample
     const uint32_t *frames;
     const double *frameE;

@@ -289,3 +289,11 @@ def test_full_L32_workload_sampled(torch_cuda):
     pick = [0, 300]
     ref = O.OracleEnsemble(work.subset(pick)).run(sweeps)
     assert_same(work, st, ms, ref, samples=pick)
+
+
+def test_row_engine_partial_waves(torch_cuda):
+    # n_T not a multiple of the walkers a wave holds (4 at L = 16, 16 at L = 8):
+    # idle lanes share waves with working ones
+    work = W.make_workload([16, 16, 16, 8, 8], [1, 5, 23, 3, 17], (0.4, 1.5), [0.1, 0.2, 0.0, 0.3, 0.1],
+                           measure_every=4, measure_start=2, name="row partial waves")
+    check(work, 18, plan=dict(chunk=6))
