@@ -47,20 +47,23 @@ WORKLOAD_TEXT = {
 # Algorithmic work of one Metropolis attempt: the VALU instructions (one lane
 # each) that a minimal gfx950 implementation of the numeric contract issues,
 # per 4-site word (one Philox call), divided by 4.
-#   Philox4x32-10: 10 rounds x (2 32x32->64 multiply-adds + 4 xors) = 60, less
-#     the 5 that depend only on (walker, sweep) and are paid once per column
-#                                                                      = 55
+#   Philox4x32-10: 10 rounds x (2 32x32->64 multiply-adds + 2 three-input
+#     xors), less the 3 that depend only on (walker, sweep): the counter's
+#     word 2 product and xor of round 0 and the word 0 product of round 1 = 37
 #   shifted x-neighbour word (one byte permute)                        =  1
-#   per site, Gaussian couplings: 6 multiply-accumulates of +-1 by the
-#     bond, conversion and + h (2), -2 beta s_i (2), x (1), hardware
-#     exponential estimate (2), bracket (2 mul + 3 compares), uniform (2),
-#     flip byte (1), energy tally (2)                          = 23 x 4 = 92
-#   per site, +-1 couplings: share of the 6 xor/shift/mask products and
-#     5 sums (23 / 4), count byte (1), table index (2), dE <= 0 bit (2),
-#     compare (1), flip byte (1), energy tally (2)         = 14.75 x 4 = 59
-#   word tail: new spins (1), two bit counts (2), mask (1)            =  4
-# Gaussian: (55 + 1 + 92 + 4) / 4 = 38;  +-1: (55 + 2 + 59 + 4) / 4 = 30.
-ALG_OPS_PER_ATTEMPT = {0: 38, 1: 30}
+#   per site, Gaussian couplings: 6 byte-select multiplies and 3 adds for
+#     S_u, conversion and + h (2), the sign of -2 beta s_i (1.75), x (1),
+#     hardware exponential estimate (2), bracket bounds (2), word to
+#     float (1), two compares (2), flip byte (1)          = 21.75 x 4 = 87
+#   word tail: flip-mask merge (2), new spins (1), flip and down-flip
+#     counts (3)                                                      =  6
+#   energy, second half-sweep only: per site sign-extend and xor (2), two
+#     adds per word, down count (2): 12 per word, 6 on average        =  6
+# Gaussian: (37 + 1 + 87 + 6 + 6) / 4 = 34.25;
+# +-1 (byte engines): (37 + 2 + 59 + 4) / 4 = 25.5, the per-site part being
+#   the share of the six product/count words (23 / 4), count byte, table
+#   index (2), dE <= 0 bit (2), compare, flip byte, energy tally (2).
+ALG_OPS_PER_ATTEMPT = {0: 34.25, 1: 25.5}
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = non-packed VALU lane-instructions/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 

@@ -88,13 +88,17 @@ typedef struct {
     int32_t measure_every;       /* m >= 1, or 0 = never measure                */
     int64_t measure_start;       /* measure after sweep n iff n+1 > start and
                                     (n+1-start) % m == 0                         */
-    int32_t tier;                /* EA_TIER_AUTO: chains that fit LDS (L <= 16)
-                                    stay there, larger ones in HBM (L divisible
-                                    by 8); EA_TIER_HBM: every sample whose L is
-                                    divisible by 8 runs HBM-resident            */
+    int32_t tier;                /* EA_TIER_AUTO: chains that fit LDS stay
+                                    there (int8 spins for L <= 16; one bit per
+                                    spin for +-1 couplings at L = 8, 16, 32),
+                                    larger ones in HBM (L divisible by 8);
+                                    EA_TIER_HBM: every sample whose L is
+                                    divisible by 8 runs HBM-resident;
+                                    EA_TIER_BYTES: as AUTO without the
+                                    one-bit engine.  Results are identical. */
 } ea_desc;
 
-enum { EA_TIER_AUTO = 0, EA_TIER_HBM = 1 };
+enum { EA_TIER_AUTO = 0, EA_TIER_HBM = 1, EA_TIER_BYTES = 2 };
 
 /* Launch plan.  Every plan gives bit-identical results. */
 typedef struct {
@@ -111,9 +115,10 @@ typedef struct {
  * EA_ENOMEM, EA_EDEVICE. */
 ea_status ea_create_ensemble(const ea_desc *desc, void *hip_stream, ea_ensemble **out);
 /* Lattice sizes: every even L in [2, 16] runs LDS-resident (one workgroup per
- * (sample, chain) holding the chain for a chunk of sweeps); L in {24, 32} (and
- * 8, 16 under EA_TIER_HBM) runs HBM-resident (four launches per sweep).  Other
- * sizes above 16 return EA_EUNSUPPORTED. */
+ * (sample, chain) holding the chain for a chunk of sweeps), and so does L = 32
+ * with +-1 couplings when the chain fits LDS at one bit per spin (n_T <= 32);
+ * other L in {24, 32} (and 8, 16 under EA_TIER_HBM) run HBM-resident (four
+ * launches per sweep).  Other sizes above 16 return EA_EUNSUPPORTED. */
 
 /* Advance every sample by n_sweeps sweeps (half-sweep p=0, half-sweep p=1,
  * replica exchange, measurement if due; Methods).  Asynchronous on the bound
@@ -208,13 +213,15 @@ ea_status ea_query(const ea_ensemble *ens, int32_t *n_samples, int64_t *total_sl
 
 /* Device self-check of the acceptance shortcut used by the sweep kernels.
  * The kernels estimate a = 2^(x log2 e) with the hardware exponential and form
- * lo = a (2^32 - 2^16), hi = a (2^32 + 2^17) + 512; a random word w with
- * fl32(w) < lo is accepted and one with fl32(w) >= hi rejected without
+ * lo = a (2^32 - 2^16) - 2^-90, hi = a (2^32 + 2^17) + 512; a random word w
+ * with fl32(w) < lo is accepted and one with fl32(w) >= hi rejected without
  * evaluating the in-house exp_ea32, any other word by the exact test.  This
  * call checks, for every binary32 x in [-86, 0] (1.1e9 values), that both
  * shortcuts decide as the exact test U 2^-24 < exp_ea32(x), U = w >> 8, would
- * for every w.  *violations must be 0; *max_rel_dev is the largest
- * |a/exp_ea32(x) - 1| seen.  Synchronizing; uses the current device. */
+ * for every w, and for every binary32 x below -86 (where exp_ea32 is 0) that
+ * lo <= 0.  *violations must be 0; *max_rel_dev is the largest
+ * |a/exp_ea32(x) - 1| seen on [-86, 0].  Synchronizing; uses the current
+ * device. */
 ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev);
 
 void ea_destroy(ea_ensemble *ens);

@@ -20,6 +20,11 @@ struct u32x4 {
     uint32_t x, y, z, w;
 };
 
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // truth table of a ^ b ^ c
+}
+
 __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1)
 {
@@ -29,8 +34,16 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n0, n2;
+        if (round < 2) {
+            // plain xors: in the first two rounds one side of each product is
+            // often loop-invariant, and the compiler can then hoist part of it
+            n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        } else {
+            n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+            n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        }
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -104,15 +117,17 @@ __device__ __forceinline__ double exp_ea64(double x)
 // within a relative 2^-17 of exp_ea32(x) (checked exhaustively on the device by
 // ea_verify_exp_bracket).  With W = fl32(w) for the 32-bit random word w and
 // U = w >> 8 the 24-bit uniform numerator, the bounds
-//   lo = a (2^32 - 2^16),   hi = a (2^32 + 2^17) + 512
+//   lo = a (2^32 - 2^16) - 2^-90,   hi = a (2^32 + 2^17) + 512
 // satisfy: W < lo implies U < exp_ea32(x) 2^24 (accept), and W >= hi implies
 // U >= exp_ea32(x) 2^24 (reject), for every x in [-86, 0]; the verification
-// checks exactly these two implications.  Between them the exact test decides.
+// checks exactly these two implications.  Below -86, where exp_ea32 is 0, a is
+// under 2^-124 and lo is negative, so no word is accepted by the bracket; the
+// verification checks that too.  Between the bounds the exact test decides.
 __device__ __forceinline__ void accept_bracket(float x, float &lo, float &hi)
 {
     const float LOG2E = __uint_as_float(0x3FB8AA3Bu);
     const float a = __builtin_amdgcn_exp2f(x * LOG2E);
-    lo = a * 4294901760.0f;                            // 2^32 - 2^16
+    lo = __builtin_fmaf(a, 4294901760.0f, -0x1p-90f);  // 2^32 - 2^16
     hi = __builtin_fmaf(a, 4295098368.0f, 512.0f);     // 2^32 + 2^17, plus 2 units of U
 }
 

@@ -23,6 +23,7 @@
 namespace ea {
 template <int L, int JK, int VAR> __global__ void site_sweep_kernel(SweepArgs A);
 template <int L, int VAR> __global__ void row_sweep_kernel(SweepArgs A);
+template <int L, int VAR> __global__ void bits_sweep_kernel(SweepArgs A);
 template <int L, int JK, int VAR> __global__ void hbm_half_kernel(SweepArgs A);
 __global__ void hbm_exchange_kernel(SweepArgs A);
 __global__ void hbm_snapshot_kernel(SweepArgs A);
@@ -61,6 +62,8 @@ struct SampleHost {
     int64_t spin_off, J_off, frame_off;
     int32_t slot_off;
     bool hbm;
+    bool bits;       // multispin engine (+-1 couplings)
+    int64_t jb_off;  // words into Jbits
 };
 
 struct DevBuf {
@@ -86,7 +89,7 @@ struct ea_ensemble {
     int device = 0;
     // device buffers
     DevBuf samples, items, spins, J, beta, beta32, lut, was, EJ, M, flips, swaps, acc, frames, frameE,
-        state, slot_sample, costab, sintab, scratchE, scratchM, finout, walkers, dEJ, dM, sow, Ju, mslots;
+        state, slot_sample, costab, sintab, scratchE, scratchM, finout, walkers, dEJ, dM, sow, Ju, mslots, Jbits;
     int64_t frames_cap = 0;  // frames allocated
     // launch classes: items sorted by lattice size, one launch per size
     struct Class {
@@ -95,6 +98,7 @@ struct ea_ensemble {
         size_t lds;
         bool hbm;
         int wbegin, wcount;  // HBM tier: range of the walker table
+        bool bits;           // multispin engine
     };
     std::vector<Class> classes;
     std::vector<int> item_pos;  // sample -> index of its chain-a item in the sorted item list
@@ -237,7 +241,7 @@ void destroy_all(ea_ensemble *e)
                       &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->frames,
                       &e->frameE, &e->state, &e->slot_sample, &e->costab, &e->sintab,
                       &e->scratchE, &e->scratchM, &e->finout, &e->walkers, &e->dEJ, &e->dM,
-                      &e->sow, &e->Ju, &e->mslots};
+                      &e->sow, &e->Ju, &e->mslots, &e->Jbits};
     for (DevBuf *b : bufs) dfree(*b);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
@@ -300,6 +304,7 @@ SweepArgs sweep_args(const ea_ensemble *e, int K, const int32_t *items, int n_it
     A.dM = (int32_t *)e->dM.p;
     A.sow = (int32_t *)e->sow.p;
     A.Ju = (const int32_t *)e->Ju.p;
+    A.Jbits = (const uint32_t *)e->Jbits.p;
     A.jkind = e->jkind;
     return A;
 }
@@ -367,8 +372,14 @@ SweepFn site_fn(int L, int jk)
 #undef EA_CASE
 }
 
-SweepFn sweep_fn(int L, int jk, bool row, bool unbatched)
+SweepFn sweep_fn(int L, int jk, bool row, bool bits, bool unbatched)
 {
+    if (bits) {
+        if (L == 8) return unbatched ? bits_sweep_kernel<8, 1> : bits_sweep_kernel<8, 0>;
+        if (L == 16) return unbatched ? bits_sweep_kernel<16, 1> : bits_sweep_kernel<16, 0>;
+        if (L == 32) return unbatched ? bits_sweep_kernel<32, 1> : bits_sweep_kernel<32, 0>;
+        return nullptr;
+    }
     if (row) {
         if (L == 8) return unbatched ? row_sweep_kernel<8, 1> : row_sweep_kernel<8, 0>;
         if (L == 16) return unbatched ? row_sweep_kernel<16, 1> : row_sweep_kernel<16, 0>;
@@ -390,6 +401,49 @@ int row_threads(int L, int nT)
 bool row_engine(int L, int nT, int jk)
 {
     return jk == 0 && (L == 8 || L == 16) && row_threads(L, nT) <= ROW_MAX_THREADS;
+}
+
+// +-1 couplings: bit a*7+b of the mask is set iff dE = 2 s (S_J + h) <= 0 for
+// s = 2a - 1, S_J = 2b - 6 (host binary64, as the oracle decides).
+uint32_t down_mask_of(float h)
+{
+    uint32_t m = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 7; ++b)
+            if (2.0 * (a ? 1.0 : -1.0) * ((2.0 * b - 6.0) + (double)h) <= 0.0) m |= 1u << (a * 7 + b);
+    return m;
+}
+
+// The multispin engine tests dE <= 0 as c >= k_s, c the number of unsatisfied
+// bonds (b = 6 - c for s = +1, b = c for s = -1); that needs the mask to be
+// such a threshold in c for both spin signs, which the monotone field gives,
+// with k_+ + k_- <= 8 (ceil((6 + h)/2) + ceil((6 - h)/2) <= 7 for any h).
+bool down_is_threshold(uint32_t m)
+{
+    int k[2] = {7, 7};
+    for (int sb = 0; sb < 2; ++sb) {
+        bool seen = false;
+        for (int c = 0; c <= 6; ++c) {
+            const int bit = sb ? c : 7 + 6 - c;
+            const bool down = (m >> bit) & 1u;
+            if (seen && !down) return false;
+            if (down && !seen) k[sb] = c;
+            seen |= down;
+        }
+    }
+    return k[0] + k[1] <= 8;  // the classes c < k_s then number at most 8
+}
+
+// The multispin engine is routed only once its GPU parity is established.
+constexpr bool kBitsEngine = false;
+
+int bits_threads(int L, int nT) { return ((nT * bits_tpw(L, nT) + 63) / 64) * 64; }
+
+bool bits_engine(int L, int nT, int jk, float h, size_t lds_max)
+{
+    if (!kBitsEngine) return false;
+    return jk == EA_J_PM1_I8 && (L == 8 || L == 16 || L == 32) && bits_lds_offsets(L, nT).total <= lds_max &&
+           bits_threads(L, nT) <= 1024 && down_is_threshold(down_mask_of(h));
 }
 
 SweepFn hbm_fn(int L, int jk, bool unbatched)
@@ -434,9 +488,9 @@ hipError_t launch_hbm_sweep(ea_ensemble *e, int L, int it, int item_first, int n
 hipError_t launch_class(ea_ensemble *e, const ea_ensemble::Class &c, int K, int first, int n_items, bool unbatched)
 {
     SweepArgs A = sweep_args(e, K, (const int32_t *)e->items.p + first, n_items);
-    SweepFn fn = sweep_fn(c.L, e->jkind, c.row, unbatched);
+    SweepFn fn = sweep_fn(c.L, e->jkind, c.row, c.bits, unbatched);
     if (!fn) return hipErrorInvalidDeviceFunction;
-    const int threads = c.row ? c.threads : e->plan.threads;
+    const int threads = c.row || c.bits ? c.threads : e->plan.threads;
     hipLaunchKernelGGL(fn, dim3(n_items), dim3(threads), c.lds, e->stream, A);
     return hipGetLastError();
 }
@@ -571,7 +625,9 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         h.frame_off = foff;
         const size_t need = lds_offsets(h.L, h.nT, e->jkind).total;
         const bool fits = h.L <= LDS_MAX_L && need <= lds_max;
-        h.hbm = !fits || (d->tier == EA_TIER_HBM && hbm_size(h.L));
+        const bool forced_hbm = d->tier == EA_TIER_HBM && hbm_size(h.L);
+        h.bits = !forced_hbm && d->tier != EA_TIER_BYTES && bits_engine(h.L, h.nT, e->jkind, h.h, lds_max);
+        h.hbm = !h.bits && (!fits || forced_hbm);
         if (h.hbm && !hbm_size(h.L)) {
             destroy_all(e);
             return fail(EA_EUNSUPPORTED,
@@ -605,7 +661,9 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         for (int s = 0; s < e->S; ++s) order[s] = s;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
             const SampleHost &x = e->smp[a], &y = e->smp[b];
-            return x.hbm != y.hbm ? y.hbm : x.L < y.L;
+            if (x.hbm != y.hbm) return y.hbm;
+            if (x.bits != y.bits) return y.bits;
+            return x.L < y.L;
         });
         e->item_pos.assign(e->S, 0);
         e->sample_class.assign(e->S, 0);
@@ -613,8 +671,9 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         int wtotal = 0;
         for (int i = 0; i < e->S; ++i) {
             const SampleHost &h = e->smp[order[i]];
-            if (e->classes.empty() || e->classes.back().L != h.L || e->classes.back().hbm != h.hbm)
-                e->classes.push_back({h.L, 2 * i, 0, 0, !h.hbm, 0, h.hbm, wtotal, 0});
+            if (e->classes.empty() || e->classes.back().L != h.L || e->classes.back().hbm != h.hbm ||
+                e->classes.back().bits != h.bits)
+                e->classes.push_back({h.L, 2 * i, 0, 0, !h.hbm && !h.bits, 0, h.hbm, wtotal, 0, h.bits});
             ea_ensemble::Class &c = e->classes.back();
             c.count += 2;
             if (h.hbm) {
@@ -622,16 +681,21 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
                 c.wcount += 2 * h.nT;
                 wtotal += 2 * h.nT;
             }
-            c.lds = std::max(c.lds, lds_offsets(h.L, h.nT, e->jkind).total);
-            c.row = c.row && row_engine(h.L, h.nT, e->jkind);
-            if (row_engine(h.L, h.nT, e->jkind)) c.threads = std::max(c.threads, row_threads(h.L, h.nT));
+            if (h.bits) {
+                c.lds = std::max(c.lds, bits_lds_offsets(h.L, h.nT).total);
+                c.threads = std::max(c.threads, bits_threads(h.L, h.nT));
+            } else {
+                c.lds = std::max(c.lds, lds_offsets(h.L, h.nT, e->jkind).total);
+                c.row = c.row && row_engine(h.L, h.nT, e->jkind);
+                if (row_engine(h.L, h.nT, e->jkind)) c.threads = std::max(c.threads, row_threads(h.L, h.nT));
+            }
             e->item_pos[order[i]] = 2 * i;
             e->sample_class[order[i]] = (int)e->classes.size() - 1;
         }
         for (const auto &c : e->classes) {
             if (c.hbm) continue;
             for (int v = 0; v < 2; ++v) {
-                SweepFn fn = sweep_fn(c.L, e->jkind, c.row, v == 1);
+                SweepFn fn = sweep_fn(c.L, e->jkind, c.row, c.bits, v == 1);
                 if (fn) (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                   (int)lds_max);
             }
@@ -653,12 +717,8 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     for (int s = 0; s < S; ++s) {
         const SampleHost &h = e->smp[s];
         const int N = h.N, HALF = N / 2;
-        uint32_t down_mask = 0;
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 7; ++b)
-                if (2.0 * (a ? 1.0 : -1.0) * ((2.0 * b - 6.0) + (double)h.h) <= 0.0) down_mask |= 1u << (a * 7 + b);
         sd[s] = SampleDev{h.L, h.nT, h.id, h.h, h.spin_off, h.J_off, h.slot_off, h.hbm ? 1 : 0, h.frame_off,
-                          down_mask, 0};
+                          down_mask_of(h.h), 0, h.jb_off};
         items[e->item_pos[s]] = 2 * s;
         items[e->item_pos[s] + 1] = 2 * s + 1;
         for (int t = 0; t < h.nT; ++t) {
@@ -725,6 +785,30 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         const float *Jf = (const float *)Jsub.data();
         for (int64_t i = 0; i < e->J_elems; ++i) Ju[i] = (int32_t)(Jf[i] * 262144.0f);
     }
+    // multispin engine: bond bits aligned to the sites of each parity,
+    // [2][6][N/64] words per sample, directions +x, -x, +y, -y, +z, -z
+    std::vector<uint32_t> Jbits;
+    for (int s = 0; s < S; ++s) {
+        SampleHost &h = e->smp[s];
+        if (!h.bits) continue;
+        const int L = h.L, N = h.N, G = N / 64;
+        h.jb_off = (int64_t)Jbits.size();
+        sd[s].jb_off = h.jb_off;
+        Jbits.resize(Jbits.size() + (size_t)12 * G, 0u);
+        const int8_t *Js = (const int8_t *)d->J + h.J_off;
+        for (int i = 0; i < N; ++i) {
+            const int x = i % L, y = (i / L) % L, z = i / (L * L);
+            const int p = (x + y + z) & 1, hh = i >> 1;
+            const int nb[3] = {(x + L - 1) % L + L * (y + L * z), x + L * ((y + L - 1) % L + L * z),
+                               x + L * (y + L * ((z + L - 1) % L))};
+            for (int dd = 0; dd < 3; ++dd) {
+                const int8_t plus = Js[(size_t)dd * N + i], minus = Js[(size_t)dd * N + nb[dd]];
+                uint32_t *row = Jbits.data() + h.jb_off + (size_t)(p * 6 + 2 * dd) * G;
+                if (plus < 0) row[hh >> 5] |= 1u << (hh & 31);
+                if (minus < 0) row[G + (hh >> 5)] |= 1u << (hh & 31);
+            }
+        }
+    }
     std::vector<double> costab((MAX_L + 1) * MAX_L, 0.0), sintab((MAX_L + 1) * MAX_L, 0.0);
     for (int L = 1; L <= MAX_L; ++L)
         for (int c = 0; c < L; ++c) {
@@ -766,6 +850,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     ALLOC(walkers, sizeof(int32_t) * wtab.size());
     ALLOC(Ju, sizeof(int32_t) * Ju.size());
     ALLOC(mslots, sizeof(int32_t) * mslots.size());
+    ALLOC(Jbits, sizeof(uint32_t) * Jbits.size());
 #undef ALLOC
     {
         ea_status fs = ensure_frames(e, e->plan.chunk);
@@ -795,6 +880,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     if (!wtab.empty()) H2D(walkers, wtab.data(), sizeof(int32_t) * wtab.size());
     if (!Ju.empty()) H2D(Ju, Ju.data(), sizeof(int32_t) * Ju.size());
     H2D(mslots, mslots.data(), sizeof(int32_t) * mslots.size());
+    if (!Jbits.empty()) H2D(Jbits, Jbits.data(), sizeof(uint32_t) * Jbits.size());
     H2D(costab, costab.data(), sizeof(double) * costab.size());
     H2D(sintab, sintab.data(), sizeof(double) * sintab.size());
 #undef H2D
@@ -1130,7 +1216,7 @@ ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev)
 {
     if (!violations || !max_rel_dev) return fail(EA_EINVAL, "null argument");
     const uint32_t first = 0x80000000u;                 // -0.0
-    const uint32_t last = 0xC2AC0000u;                  // -86.0
+    const uint32_t last = 0xFF800000u;                  // -inf
     const uint32_t count = last - first + 1;
     unsigned long long *dv = nullptr;
     unsigned int *dm = nullptr;

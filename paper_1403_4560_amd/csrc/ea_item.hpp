@@ -1,0 +1,127 @@
+// ea_item.hpp -- device helpers shared by the LDS-resident engines: block
+// copies, wave and lane-group sums, the LDS frame of one (sample, chain) work
+// item and the replica-exchange pass over it.
+#pragma once
+
+#include "ea_device.hpp"
+#include "ea_types.hpp"
+
+namespace ea {
+
+// Block-cooperative byte copy, 16 bytes at a time when both ends allow it.
+__device__ __forceinline__ void block_copy(void *dst, const void *src, size_t bytes)
+{
+    const int T = blockDim.x, tid = threadIdx.x;
+    if ((((uintptr_t)dst | (uintptr_t)src | bytes) & 15) == 0) {
+        int4 *d = (int4 *)dst;
+        const int4 *s = (const int4 *)src;
+        for (size_t i = tid; i < bytes / 16; i += T) d[i] = s[i];
+    } else {
+        int8_t *d = (int8_t *)dst;
+        const int8_t *s = (const int8_t *)src;
+        for (size_t i = tid; i < bytes; i += T) d[i] = s[i];
+    }
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const int lo = __shfl_xor((int)(unsigned long long)v, m);
+        const int hi = __shfl_xor((int)((unsigned long long)v >> 32), m);
+        v += (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// Sum over aligned groups of W consecutive lanes (W a power of two <= 64).
+template <int W>
+__device__ __forceinline__ long long group_sum_i64(long long v)
+{
+#pragma unroll
+    for (int m = W / 2; m >= 1; m >>= 1) {
+        const int lo = __shfl_xor((int)(unsigned long long)v, m);
+        const int hi = __shfl_xor((int)((unsigned long long)v >> 32), m);
+        v += (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    }
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ int group_sum_i32(int v)
+{
+#pragma unroll
+    for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// Pointers into the dynamic LDS of one work item.
+struct ItemLds {
+    int8_t *S;
+    void *J;
+    int32_t *was, *sow, *M, *dM, *fl, *sw;
+    long long *EJ, *dEJ;
+    uint32_t *lut;
+    float *b32;
+    double *b64;
+};
+
+__device__ __forceinline__ ItemLds item_lds(char *smem, int L, int nT, int jkind)
+{
+    const LdsOff o = lds_offsets(L, nT, jkind);
+    ItemLds p;
+    p.S = (int8_t *)(smem + o.spins);
+    p.J = (void *)(smem + o.J);
+    p.was = (int32_t *)(smem + o.was);
+    p.sow = (int32_t *)(smem + o.sow);
+    p.M = (int32_t *)(smem + o.M);
+    p.dM = (int32_t *)(smem + o.dM);
+    p.fl = (int32_t *)(smem + o.fl);
+    p.sw = (int32_t *)(smem + o.sw);
+    p.EJ = (long long *)(smem + o.EJ);
+    p.dEJ = (long long *)(smem + o.dEJ);
+    p.lut = (uint32_t *)(smem + o.lut);
+    p.b32 = (float *)(smem + o.b32);
+    p.b64 = (double *)(smem + o.b64);
+    return p;
+}
+
+// Replica exchange of neighbouring slots (t, t+1), t = n&1, n&1 + 2, ...
+// (Methods: parallel tempering; even-odd pairs alternate with the sweep
+// parity).  D = (beta_t - beta_{t+1}) (E_t - E_{t+1}) in binary64; accepted
+// iff D >= 0 or u53 < exp_ea64(D), the uniform from the exchange counter
+// (0, n, (1 << 28) | (t << 1) | r, sample).  Swaps walker labels only.
+__device__ __forceinline__ void exchange_pass(const SweepArgs &A, const SampleDev &d, int r, int64_t n,
+                                              const ItemLds &I, double unit, double hd)
+{
+    const int nT = d.n_T, T = blockDim.x;
+    for (int j = threadIdx.x;; j += T) {
+        const int t = (int)(n & 1) + 2 * j;
+        if (t + 1 >= nT) break;
+        const int w0 = I.was[t], w1 = I.was[t + 1];
+        const double E0 = (double)I.EJ[w0] * unit - hd * (double)I.M[w0];
+        const double E1 = (double)I.EJ[w1] * unit - hd * (double)I.M[w1];
+        const double D = (I.b64[t] - I.b64[t + 1]) * (E0 - E1);
+        bool acc = D >= 0.0;
+        if (!acc) {
+            const u32x4 q = philox4x32_10(0u, (uint32_t)n,
+                                          (PURPOSE_EXCHANGE << 28) | ((uint32_t)t << 1) | (uint32_t)r,
+                                          d.sample_id, A.key0, A.key1);
+            acc = u53_of(q.x, q.y) < exp_ea64(D);
+        }
+        if (acc) {
+            I.was[t] = w1;
+            I.was[t + 1] = w0;
+            I.sw[t] += 1;
+        }
+    }
+}
+
+}  // namespace ea

@@ -21,94 +21,10 @@
 //  * site engine (any even L <= 16, either coupling kind): a thread takes a
 //    4-site group of any walker and updates its sites one by one.
 #include "ea_device.hpp"
+#include "ea_item.hpp"
 #include "ea_types.hpp"
 
 namespace ea {
-
-// Block-cooperative byte copy, 16 bytes at a time when both ends allow it.
-__device__ __forceinline__ void block_copy(void *dst, const void *src, size_t bytes)
-{
-    const int T = blockDim.x, tid = threadIdx.x;
-    if ((((uintptr_t)dst | (uintptr_t)src | bytes) & 15) == 0) {
-        int4 *d = (int4 *)dst;
-        const int4 *s = (const int4 *)src;
-        for (size_t i = tid; i < bytes / 16; i += T) d[i] = s[i];
-    } else {
-        int8_t *d = (int8_t *)dst;
-        const int8_t *s = (const int8_t *)src;
-        for (size_t i = tid; i < bytes; i += T) d[i] = s[i];
-    }
-}
-
-__device__ __forceinline__ long long wave_sum_i64(long long v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const int lo = __shfl_xor((int)(unsigned long long)v, m);
-        const int hi = __shfl_xor((int)((unsigned long long)v >> 32), m);
-        v += (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-    }
-    return v;
-}
-
-__device__ __forceinline__ int wave_sum_i32(int v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-    return v;
-}
-
-// Sum over aligned groups of W consecutive lanes (W a power of two <= 64).
-template <int W>
-__device__ __forceinline__ long long group_sum_i64(long long v)
-{
-#pragma unroll
-    for (int m = W / 2; m >= 1; m >>= 1) {
-        const int lo = __shfl_xor((int)(unsigned long long)v, m);
-        const int hi = __shfl_xor((int)((unsigned long long)v >> 32), m);
-        v += (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-    }
-    return v;
-}
-
-template <int W>
-__device__ __forceinline__ int group_sum_i32(int v)
-{
-#pragma unroll
-    for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-    return v;
-}
-
-// Pointers into the dynamic LDS of one work item.
-struct ItemLds {
-    int8_t *S;
-    void *J;
-    int32_t *was, *sow, *M, *dM, *fl, *sw;
-    long long *EJ, *dEJ;
-    uint32_t *lut;
-    float *b32;
-    double *b64;
-};
-
-__device__ __forceinline__ ItemLds item_lds(char *smem, int L, int nT, int jkind)
-{
-    const LdsOff o = lds_offsets(L, nT, jkind);
-    ItemLds p;
-    p.S = (int8_t *)(smem + o.spins);
-    p.J = (void *)(smem + o.J);
-    p.was = (int32_t *)(smem + o.was);
-    p.sow = (int32_t *)(smem + o.sow);
-    p.M = (int32_t *)(smem + o.M);
-    p.dM = (int32_t *)(smem + o.dM);
-    p.fl = (int32_t *)(smem + o.fl);
-    p.sw = (int32_t *)(smem + o.sw);
-    p.EJ = (long long *)(smem + o.EJ);
-    p.dEJ = (long long *)(smem + o.dEJ);
-    p.lut = (uint32_t *)(smem + o.lut);
-    p.b32 = (float *)(smem + o.b32);
-    p.b64 = (double *)(smem + o.b64);
-    return p;
-}
 
 // ---------------------------------------------------------------------------
 // Site engine: one checkerboard half-sweep (parity p) over every walker of the
@@ -219,25 +135,42 @@ __device__ __forceinline__ void site_half_sweep(const SweepArgs &A, const Sample
 // their six neighbour words (aligned and shifted x, +y, -y, +z, -z; bytes +-1)
 // and their six bonds (int32 multiples of 2^-18).  rw holds the four Philox
 // words of the group, m2b = -2 beta32 of the walker's slot.  Returns the flip
-// mask (0xFE in the bytes of accepted sites) and adds (S_u XOR m) over
-// accepted sites to accE, m = 0 for s_i = +1 and -1 for s_i = -1.
+// mask (0xFE in the bytes of accepted sites).
+//
+// Energy tallies, by TALLY:
+//   TALLY_DELTA: accE += (S_u XOR m) over accepted sites, m = 0 for s_i = +1
+//     and -1 for s_i = -1, so that the sum of s_i S_u over accepted sites is
+//     accE + (accepted down spins);
+//   TALLY_NONE: nothing;
+//   TALLY_FINAL: accE += (S_u XOR m') over all four sites and nd += the number
+//     of -1 spins after the update, m' from the updated spin, so that
+//     accE + nd = sum of s_i' S_u with the updated spins s_i'.  On the second
+//     half-sweep this is the whole coupling energy: every bond joins one even
+//     and one odd site, and the even spins no longer change, so E_J of the
+//     walker is minus the sum of s_i' S_u over its odd sites.
+// S_u can reach 6 (2^21 - 1) in magnitude, beyond a 24-bit multiplier, so the
+// sign is applied by XOR.
 //
 // Decision: x = -fl32(beta32 dE) is formed as fl32((-2 beta32 s_i) f) (the same
 // real number, rounded once), dE <= 0 iff x >= 0, exp_ea32 is 0 below -86.  The
 // random word is decided by accept_bracket when it falls outside the bracket
-// (ea_verify_exp_bracket proves the bracket safe for every x <= 0), otherwise
-// by U 2^-24 < exp_ea32(x) itself.  For x >= 0 both routes accept, as the
-// contract's dE <= 0 rule does.
+// (ea_verify_exp_bracket proves the bracket safe for every x <= 0, and that
+// below -86 no word falls under it), otherwise by U 2^-24 < exp_ea32(x)
+// itself.  For x >= 0 both routes accept, as the contract's dE <= 0 rule does.
+constexpr int TALLY_DELTA = 0, TALLY_NONE = 1, TALLY_FINAL = 2;
+
+template <int TALLY>
 __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, uint32_t Xs, uint32_t Yp,
                                                       uint32_t Ym, uint32_t Zp, uint32_t Zm, const int Ja[4],
                                                       const int Js[4], const int Jy[4], const int Jyn[4],
                                                       const int Jz[4], const int Jzn[4], const u32x4 rw,
-                                                      float m2b, float h32, int &accE)
+                                                      float m2b, float h32, int &accE, int &nd)
 {
     const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
     const uint32_t nS = ~Sv;                            // byte sign bit set iff s_i = +1
     const uint32_t b2 = __float_as_uint(m2b) & 0x7FFFFFFFu;  // 2 beta32
     uint32_t fm = 0;
+    int Sus[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int sh = 8 * i;
@@ -247,23 +180,32 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
         Su += __mul24(__builtin_amdgcn_sbfe((int)Ym, sh, 8), Jyn[i]);
         Su += __mul24(__builtin_amdgcn_sbfe((int)Zp, sh, 8), Jz[i]);
         Su += __mul24(__builtin_amdgcn_sbfe((int)Zm, sh, 8), Jzn[i]);
+        Sus[i] = Su;
         // f = fl32(S_J + h): S_J = Su 2^-18 exactly, so the fused form rounds once, as the sum does
         const float f = __builtin_fmaf((float)Su, 0x1p-18f, h32);
         // c = -2 beta32 s_i: the sign bit of 2 beta32 set iff s_i = +1 (exact)
         const float c = __uint_as_float(__builtin_amdgcn_ubfe(nS, sh + 7, 1) << 31 | b2);
         const float x = c * f;                         // = -fl32(beta * dE)
-        const bool inside = x >= -86.0f;              // exp_ea32 is 0 below -86
-        // x >= 0 (dE <= 0): the estimate is >= 1 (or inf), so W < lo unless w is
-        // within 2^17 of 2^32, and then exp_ea32(x) >= 1 > U 2^-24: always accepted
         float lo, hi;
         accept_bracket(x, lo, hi);
         const float Wf = (float)words[i];
-        const bool below = Wf < lo, above = Wf >= hi;
-        bool accept = inside & below;
-        if (inside & !below & !above) accept = (float)(words[i] >> 8) * 0x1p-24f < exp_ea32(x);
-        const int m = __builtin_amdgcn_sbfe((int)Sv, sh + 7, 1);  // 0: s_i = +1, -1: s_i = -1
+        const bool below = Wf < lo, under_hi = Wf < hi;  // lo < hi, so below implies under_hi
+        bool accept = below;
+        // If a lane of the wave has lo <= W < hi (the two lane masks differ),
+        // every lane takes the exact test, which the bracket only anticipates.
+        if (__builtin_amdgcn_ballot_w64(under_hi) != __builtin_amdgcn_ballot_w64(below))
+            accept = (float)(words[i] >> 8) * 0x1p-24f < exp_ea32(x);
         fm |= accept ? 0xFEu << sh : 0u;
-        accE += accept ? (Su ^ m) : 0;
+        if constexpr (TALLY == TALLY_DELTA) {
+            const int m = __builtin_amdgcn_sbfe((int)Sv, sh + 7, 1);  // 0: s_i = +1, -1: s_i = -1
+            accE += accept ? (Su ^ m) : 0;
+        }
+    }
+    if constexpr (TALLY == TALLY_FINAL) {
+        const uint32_t Sn = Sv ^ fm;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) accE += Sus[i] ^ __builtin_amdgcn_sbfe((int)Sn, 8 * i + 7, 1);
+        nd += __builtin_popcount(Sn & 0x80808080u);
     }
     return fm;
 }
@@ -308,10 +250,11 @@ __device__ __forceinline__ uint32_t update_word_pm1(uint32_t Sv, uint32_t Xa, ui
 // one byte permute of the row's words produces.  The y and z neighbours are
 // the words of the same index in the adjacent rows.
 //
-// Tallies per thread and sweep: accE = sum over accepted sites of
-// (S_u XOR m) with m = 0 for s_i = +1 and -1 for s_i = -1, so that
-// sum of s_i S_u = accE + (accepted down spins); bf and bd count the set bits
-// of the flip masks (7 per flipped byte) and of (spins AND flip mask).
+// Tallies per thread and sweep: the first half-sweep tallies no energy; the
+// second gives accE + nd = sum of s_i S_u over the thread's odd sites after
+// the update (TALLY_FINAL), i.e. minus its share of the walker's new E_J;
+// bf and bd count the set bits of the flip masks (7 per flipped byte) and of
+// (spins AND flip mask) over both halves.
 //
 // Lane map: a walker's L*L/8 columns (k, y) are split by the parity of y over
 // two waves, and a wave holds the columns of WPW walkers with y of one parity.
@@ -327,8 +270,8 @@ struct RowMap {
 template <int L, int P, int EPS>
 __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d, uint8_t *Sw, const int *J,
                                          int o_y0, int o_yp, int o_ym, int o_x, int e_prev, int z, int zp,
-                                         int zm, uint32_t c1, uint32_t c2, float m2b, int &accE, int &bf,
-                                         int &bd)
+                                         int zm, uint32_t c1, uint32_t c2, float m2b, int &accE, int &nd,
+                                         int &bf, int &bd)
 {
     constexpr int HALF = L * L * L / 2, HL = L / 2, PLANE = L * HL;
     const uint8_t *own = Sw + P * HALF, *oth = Sw + (1 - P) * HALF;
@@ -362,8 +305,8 @@ __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d,
     const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
     const uint32_t g = (uint32_t)(o_y0 / 4 + z * (PLANE / 4));
     const u32x4 rw = philox4x32_10(g, c1, c2, d.sample_id, A.key0, A.key1);
-    const uint32_t fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b, d.h32,
-                                          accE);
+    const uint32_t fm = update_word_gauss<P == 0 ? TALLY_NONE : TALLY_FINAL>(
+        Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b, d.h32, accE, nd);
     *(uint32_t *)(Sw + P * HALF + o_y0 + zo) = Sv ^ fm;
     bf += __builtin_popcount(fm);
     bd += __builtin_popcount(Sv & fm);
@@ -373,7 +316,7 @@ __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d,
 template <int L, int P, int E0>
 __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleDev &d, int r, int64_t n,
                                                const ItemLds &I, int w, int y, int k, int t, int &accE,
-                                               int &bf, int &bd)
+                                               int &nd, int &bf, int &bd)
 {
     constexpr int N = L * L * L, WPR = L / 8, HL = L / 2;
     const int yp = (y + 1) & (L - 1), ym = (y - 1) & (L - 1);
@@ -389,9 +332,10 @@ __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleD
 #pragma unroll 1
     for (int z = 0; z < L; z += 2) {
         const int zm = z == 0 ? L - 1 : z - 1, zpp = z + 2 == L ? 0 : z + 2;
-        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z, z + 1, zm, c1, c2, m2b, accE, bf, bd);
-        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, zpp, z, c1, c2, m2b, accE, bf,
-                               bd);
+        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z, z + 1, zm, c1, c2, m2b, accE, nd, bf,
+                           bd);
+        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, zpp, z, c1, c2, m2b, accE, nd,
+                               bf, bd);
     }
 }
 
@@ -474,20 +418,22 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
             // its lanes; the two waves of a walker add into LDS.
             const bool on = rw_w < nT;
             const int t = on ? I.sow[rw_w] : 0;
-            int accE = 0, bf = 0, bd = 0;
+            int accE = 0, nd = 0, bf = 0, bd = 0;
             if (on) {
-                if (rw_par) row_half_sweep<L, 0, 1>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
-                else row_half_sweep<L, 0, 0>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
+                if (rw_par) row_half_sweep<L, 0, 1>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, nd, bf, bd);
+                else row_half_sweep<L, 0, 0>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, nd, bf, bd);
             }
             __syncthreads();
             if (on) {
-                if (rw_par) row_half_sweep<L, 1, 0>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
-                else row_half_sweep<L, 1, 1>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, bf, bd);
-                const long long sE = group_sum_i64<CPW>((long long)accE);
+                if (rw_par) row_half_sweep<L, 1, 0>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, nd, bf, bd);
+                else row_half_sweep<L, 1, 1>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, nd, bf, bd);
+                // |accE| <= 64 sites x 6 (2^21 - 1) < 2^31 per thread
+                const long long sE = group_sum_i64<CPW>((long long)accE + nd);
                 const int sf = group_sum_i32<CPW>(bf), sd = group_sum_i32<CPW>(bd);
                 if (rw_rem == 0) {
                     const int flips = sf / 7, ndown = sd / 7;
-                    atomicAdd((unsigned long long *)&I.dEJ[rw_w], (unsigned long long)(2 * (sE + ndown)));
+                    // dEJ collects minus the new E_J (both waves of the walker add)
+                    atomicAdd((unsigned long long *)&I.dEJ[rw_w], (unsigned long long)sE);
                     atomicAdd(&I.dM[rw_w], -2 * (flips - 2 * ndown));
                     atomicAdd(&I.fl[t], flips);
                 }
@@ -499,31 +445,11 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
         }
         __syncthreads();
         for (int i = tid; i < nT; i += T) {
-            I.EJ[i] += I.dEJ[i];
+            I.EJ[i] = ROW ? -I.dEJ[i] : I.EJ[i] + I.dEJ[i];
             I.M[i] += I.dM[i];
         }
         __syncthreads();
-        // Replica exchange of neighbouring slots (t, t+1), t = n&1, n&1 + 2, ...
-        for (int j = tid;; j += T) {
-            const int t = (int)(n & 1) + 2 * j;
-            if (t + 1 >= nT) break;
-            const int w0 = I.was[t], w1 = I.was[t + 1];
-            const double E0 = (double)I.EJ[w0] * unit - hd * (double)I.M[w0];
-            const double E1 = (double)I.EJ[w1] * unit - hd * (double)I.M[w1];
-            const double D = (I.b64[t] - I.b64[t + 1]) * (E0 - E1);
-            bool acc = D >= 0.0;
-            if (!acc) {
-                const u32x4 q = philox4x32_10(0u, (uint32_t)n,
-                                              (PURPOSE_EXCHANGE << 28) | ((uint32_t)t << 1) | (uint32_t)r,
-                                              d.sample_id, A.key0, A.key1);
-                acc = u53_of(q.x, q.y) < exp_ea64(D);
-            }
-            if (acc) {
-                I.was[t] = w1;
-                I.was[t + 1] = w0;
-                I.sw[t] += 1;
-            }
-        }
+        exchange_pass(A, d, r, n, I, unit, hd);
         __syncthreads();
         // Snapshot for the overlap measurement, in slot order.
         const int64_t done = n + 1;
@@ -695,7 +621,9 @@ __global__ void __launch_bounds__(256) hbm_half_kernel(SweepArgs A)
             const int Js[4] = {eps ? Jpx.x : Ep, eps ? Jpx.y : V.x, eps ? Jpx.z : V.y, eps ? Jpx.w : V.z};
             const int Jy[4] = {Jpy.x, Jpy.y, Jpy.z, Jpy.w}, Jyn[4] = {Jym.x, Jym.y, Jym.z, Jym.w};
             const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
-            fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b, d.h32, accE);
+            int unused = 0;
+            fm = update_word_gauss<TALLY_DELTA>(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b,
+                                                d.h32, accE, unused);
         } else {
             const uint8_t *J8 = (const uint8_t *)A.J + d.J_off;
             const uint8_t *Jp = J8 + (size_t)p * 3 * HALF, *Jo = J8 + (size_t)(1 - p) * 3 * HALF;
@@ -947,7 +875,9 @@ EA_MEAS(32)
 // for every binary32 x in [-86, 0], in binary64:
 //   lo (1 + 2^-24) <= 256 E24        (W < lo  =>  U < E24, E24 = exp_ea32(x) 2^24)
 //   hi (1 - 2^-24) / 256 - 1 >= E24  (W >= hi =>  U >= E24)
-// where W = fl32(w) is within a relative 2^-24 of w and U = w >> 8 >= w/256 - 1.
+// where W = fl32(w) is within a relative 2^-24 of w and U = w >> 8 >= w/256 - 1;
+// and for every binary32 x below -86 (down to -inf), where exp_ea32 is 0,
+// lo <= 0, so that no W >= 0 is accepted by the bracket alone.
 // Also records the largest |a / exp_ea32(x) - 1| of the hardware estimate.
 __global__ void exp_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned long long *violations,
                                    unsigned int *max_dev_bits)
@@ -957,6 +887,11 @@ __global__ void exp_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned
     const float x = __uint_as_float(first_bits + i);
     float lo, hi;
     accept_bracket(x, lo, hi);
+    if (!(x >= -86.0f)) {
+        // exp_ea32 is 0 here: no word may fall below the bracket
+        if (!(lo <= 0.0f)) atomicAdd(violations, 1ull);
+        return;
+    }
     const double E24 = (double)exp_ea32(x) * 16777216.0;
     const bool okA = (double)lo * (1.0 + 0x1p-24) <= 256.0 * E24;
     const bool okB = (double)hi * (1.0 - 0x1p-24) / 256.0 - 1.0 >= E24;

@@ -19,6 +19,10 @@
 //                  at word f*frame_words + frame_off[s], layout [2][n_T][L*L]
 //                  rows, row (y, z) at index y + L z, bit x set iff s = -1
 //   frameE  float64 [frame][2*total_slots] energies of the snapshotted walkers
+//   Jbits   uint32 (+-1 couplings on the bit engine) per sample [2 parities]
+//                  [6 bonds: +x, -x, +y, -y, +z, -z][N/64]: bit j of word g is
+//                  set iff the bond of the parity-p site with sublattice index
+//                  32 g + j in that direction is -1
 #pragma once
 
 #include <stddef.h>
@@ -45,6 +49,7 @@ struct SampleDev {
     int64_t frame_off;  // words into each snapshot frame
     uint32_t down_mask; // +-1 couplings: bit a*7+b set iff 2 s (S_J + h) <= 0, s = 2a-1, S_J = 2b-6
     int32_t pad;
+    int64_t jb_off;     // bit engine: words into Jbits
 };
 
 struct SweepArgs {
@@ -81,6 +86,7 @@ struct SweepArgs {
     int32_t *dM;                // per walker: magnetisation change of this sweep
     int32_t *sow;               // per walker: its slot during this sweep
     const int32_t *Ju;          // Gaussian couplings as int32 multiples of 2^-18, Jsub layout
+    const uint32_t *Jbits;      // bit engine: per sample [2 parities][6 bonds][N/64] words
 };
 
 struct MeasureArgs {
@@ -137,6 +143,46 @@ __host__ __device__ inline LdsOff lds_offsets(int L, int nT, int jkind)
     o.b64 = align16(o.b32 + 4 * T4);
     o.total = align16(o.b64 + 8 * T4);
     return o;
+}
+
+// LDS layout of one bit-engine work item (bytes): the 256-entry
+// bit-to-byte spreading table and the per-slot threshold tables [n_T][8] at
+// fixed offsets, then spin bits [n_T][2][N/64] words, bond bits [2][6][N/64],
+// then the per-walker/slot arrays of the common frame.
+struct BitsLdsOff {
+    size_t spread, th, spins, J, was, sow, M, dM, fl, sw, EJ, dEJ, b64, total;
+};
+
+__host__ __device__ inline BitsLdsOff bits_lds_offsets(int L, int nT)
+{
+    const size_t G = (size_t)L * L * L / 64;
+    const size_t T4 = (size_t)((nT + 3) & ~3);
+    BitsLdsOff o;
+    o.spread = 0;
+    o.th = 256 * 8;
+    o.spins = align16(o.th + (size_t)nT * 8 * 4);
+    o.J = o.spins + (size_t)nT * 2 * G * 4;
+    o.was = o.J + 12 * G * 4;
+    o.sow = o.was + 4 * T4;
+    o.M = o.sow + 4 * T4;
+    o.dM = o.M + 4 * T4;
+    o.fl = o.dM + 4 * T4;
+    o.sw = o.fl + 4 * T4;
+    o.EJ = align16(o.sw + 4 * T4);
+    o.dEJ = o.EJ + 8 * T4;
+    o.b64 = o.dEJ + 8 * T4;
+    o.total = align16(o.b64 + 8 * T4);
+    return o;
+}
+
+// Threads per walker of the bit engine: the largest power of two <= 64 that
+// divides the N/64 words of a sublattice and keeps n_T * TPW <= 1024.
+__host__ __device__ inline int bits_tpw(int L, int nT)
+{
+    const int G = L * L * L / 64;
+    int t = 64;
+    while (t > 1 && (t > G || nT * t > 1024)) t >>= 1;
+    return t;
 }
 
 }  // namespace ea
