@@ -32,7 +32,7 @@ METRIC = "spin-flip attempts/ns at L=16 batched vs unbatched; bit-exact spins"
 SWEEPS_PER_STEP = 100
 KERNEL = {"L16_gauss": "row_sweep_kernel<16, 0>", "L8_gauss": "row_sweep_kernel<8, 0>",
           "L4_gauss": "site_sweep_kernel<4, 0, 0>", "mixed_L6_12": "site/row sweep kernels (4 sizes)",
-          "L32_pm1": "hbm_half_kernel<32, 1, 0> x 2 + exchange + snapshot per sweep"}
+          "L32_pm1": "bits_sweep_kernel<32, 0>"}
 WORKLOAD_TEXT = {
     "L16_gauss": "L16_gauss: L=16, 2048 samples, 24 temperatures geometric in T=[0.4,1.5], 2 replicas, "
                  "Gaussian J on the 2^-18 grid, h=0.1, measure every 10 sweeps",
@@ -41,7 +41,7 @@ WORKLOAD_TEXT = {
     "mixed_L6_12": "mixed_L6_12: 4096 samples, L in {6,8,10,12}, h in {0.1,0.2,0.3}, 16 temperatures in "
                    "T=[0.5,1.6], 2 replicas, Gaussian J",
     "L32_pm1": "L32_pm1: L=32, 512 samples, 32 temperatures in T=[0.5,2.0], 2 replicas, +-1 J, h=0.4, "
-               "HBM-resident",
+               "one bit per spin in LDS",
 }
 
 # Algorithmic work of one Metropolis attempt: the VALU instructions (one lane
@@ -59,11 +59,16 @@ WORKLOAD_TEXT = {
 #     counts (3)                                                      =  6
 #   energy, second half-sweep only: per site sign-extend and xor (2), two
 #     adds per word, down count (2): 12 per word, 6 on average        =  6
-# Gaussian: (37 + 1 + 87 + 6 + 6) / 4 = 34.25;
-# +-1 (byte engines): (37 + 2 + 59 + 4) / 4 = 25.5, the per-site part being
-#   the share of the six product/count words (23 / 4), count byte, table
-#   index (2), dE <= 0 bit (2), compare, flip byte, energy tally (2).
-ALG_OPS_PER_ATTEMPT = {0: 34.25, 1: 25.5}
+# Gaussian: (37 + 1 + 87 + 6 + 6) / 4 = 34.25.
+# +-1 couplings, one bit per spin, per 32-site word / 32:
+#   Philox 8 x 37 = 296; per site: table address (1), compare and carry-in
+#   (2) = 96; class bytes: 3 spread-table addresses (2 each) and 4 merges per
+#   8 sites = 40; neighbours (x rotations 6, x selects 2, y funnels 2), six
+#   unsatisfied-bond words (6), the count c (8), dE <= 0 (8), class planes
+#   (3), new spins (1), flip and down-flip counts (3), energy on the second
+#   half only (7, 3.5 on average) = 42.5: 474.5 / 32 = 14.83.
+ALG_OPS_PER_ATTEMPT = {"L16_gauss": 34.25, "L8_gauss": 34.25, "mixed_L6_12": 34.25, "L4_gauss": 34.25,
+                       "L32_pm1": 474.5 / 32}
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = non-packed VALU lane-instructions/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
@@ -166,10 +171,10 @@ def main():
     ens.close()
     progress("timed %d steps in %.2f s: %.1f attempts/ns" % (args.steps, dt, value))
 
-    # roofline of the dominant kernel (the LDS-resident row-engine sweep kernel)
+    # roofline of the dominant kernel (the LDS-resident sweep kernel of the workload)
     avg_launch_s = k_ms / 1e3 / max(k_launches, 1)
     attempts_per_launch = attempts_per_step  # one launch per step (chunk)
-    ops = ALG_OPS_PER_ATTEMPT[work.jkind]
+    ops = ALG_OPS_PER_ATTEMPT[args.workload]
     fp, traffic = MEASURED_TRAFFIC.get(args.workload, (None, None))
     if fp != kernel_fingerprint():
         traffic = None

@@ -111,12 +111,16 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+TIER_AUTO, TIER_HBM, TIER_BYTES = 0, 1, 2
+
+
 class Ensemble:
     """One ensemble of disorder samples on the current HIP device.
 
     ``work`` is a ``workload.Workload``; ``stream`` a raw HIP stream handle
     (e.g. ``torch.cuda.current_stream().cuda_stream``) or None for a stream
-    owned by the ensemble."""
+    owned by the ensemble; ``tier`` one of TIER_AUTO, TIER_HBM (samples with L
+    divisible by 8 HBM-resident) or TIER_BYTES (no one-bit engine)."""
 
     def __init__(self, work, stream=None, tier=0):
         lib = load()

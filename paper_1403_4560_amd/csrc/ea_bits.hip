@@ -82,6 +82,20 @@ __device__ __forceinline__ uint32_t shift_in_less(uint32_t F, uint32_t a, uint32
     return r;
 }
 
+// Loads from an LDS byte address.
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+typedef __attribute__((address_space(3))) const uint64_t lds_u64;
+__device__ __forceinline__ uint32_t lds_load(uint32_t addr) { return *(lds_u32 *)(size_t)addr; }
+__device__ __forceinline__ uint2 lds_load2(uint32_t addr)
+{
+    const uint64_t v = *(lds_u64 *)(size_t)addr;
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+__device__ __forceinline__ uint32_t lds_addr(const void *p)
+{
+    return (uint32_t)(size_t)(__attribute__((address_space(3))) const char *)p;
+}
+
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, int s)
 {
     return __builtin_amdgcn_alignbit(hi, lo, s);  // ({hi, lo} >> s) low word
@@ -108,6 +122,19 @@ __device__ __forceinline__ uint32_t spread2(uint32_t x)
     return x;
 }
 
+// Bytes 8M .. 8M + 7 of the class planes spread to byte offsets 4 e (sites
+// 8M .. 8M + 3 in Q[2M], 8M + 4 .. 8M + 7 in Q[2M + 1]); sp = LDS address of
+// the spreading table.
+template <int M>
+__device__ __forceinline__ void spread3(uint32_t sp, uint32_t E0, uint32_t E1, uint32_t E2, uint32_t Q[8])
+{
+    const uint2 t0 = lds_load2(sp + 8 * ((E0 >> (8 * M)) & 0xFFu));
+    const uint2 t1 = lds_load2(sp + 8 * ((E1 >> (8 * M)) & 0xFFu));
+    const uint2 t2 = lds_load2(sp + 8 * ((E2 >> (8 * M)) & 0xFFu));
+    Q[2 * M] = t0.x | (t1.x << 1) | (t2.x << 2);
+    Q[2 * M + 1] = t0.y | (t1.y << 1) | (t2.y << 2);
+}
+
 struct BitTally {
     int flips = 0;   // flipped sites (both halves)
     int fdown = 0;   // flipped sites that were -1 (both halves)
@@ -116,8 +143,8 @@ struct BitTally {
 
 // Metropolis update of word g (32 sites of sublattice P) of one walker.
 // Sw: the walker's bits [2][G]; JB: bond bits [2][6][G]; th_base: LDS byte
-// address of the slot's threshold table (8 entries, entry e) in the work
-// item's LDS smem; kb0/kb1: bits of k_s as all-zero/all-one masks for
+// address of the slot's threshold table (8 entries, entry e); smem: the work
+// item's LDS; kb0/kb1: bits of k_s as all-zero/all-one masks for
 // s = +1 / -1.
 template <int L, int P>
 __device__ __forceinline__ void bits_word(const SweepArgs &A, const SampleDev &d, uint32_t *Sw,
@@ -163,29 +190,23 @@ __device__ __forceinline__ void bits_word(const SweepArgs &A, const SampleDev &d
     const uint32_t D = ~w2;
     // class numbers e (c, or 7 - c for s = +1) as byte offsets 4 e, 8 sites per pair
     const uint32_t E0 = ~(C0 ^ s), E1 = ~(C1 ^ s), E2 = ~(C2 ^ s);
-    const uint2 *SP = (const uint2 *)(smem + SPREAD_OFF);
     uint32_t Q[8];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const uint2 t0 = SP[(E0 >> (8 * m)) & 0xFFu], t1 = SP[(E1 >> (8 * m)) & 0xFFu];
-        const uint2 t2 = SP[(E2 >> (8 * m)) & 0xFFu];
-        Q[2 * m] = t0.x | (t1.x << 1) | (t2.x << 2);
-        Q[2 * m + 1] = t0.y | (t1.y << 1) | (t2.y << 2);
-    }
-    // sites 31 .. 0, one Philox call per four; F collects the accept bits
-    // (w < thr), each shifted in as the carry of F + F
+    const uint32_t sp = lds_addr(smem + SPREAD_OFF);
+    spread3<0>(sp, E0, E1, E2, Q);
+    spread3<1>(sp, E0, E1, E2, Q);
+    spread3<2>(sp, E0, E1, E2, Q);
+    spread3<3>(sp, E0, E1, E2, Q);
+    // sites 31 .. 0, one Philox call per four (counter word 0 = 8 g + q); F
+    // collects the accept bits (w < thr), each shifted in as the carry of F + F
     uint32_t F = 0;
 #pragma unroll
     for (int q = 7; q >= 0; --q) {
-        const u32x4 rw = philox4x32_10((uint32_t)(8 * g + q), c1, c2, d.sample_id, A.key0, A.key1);
-        const uint32_t wd[4] = {rw.x, rw.y, rw.z, rw.w};
-#pragma unroll
-        for (int i = 3; i >= 0; --i) {
-            const int j = 4 * q + i;
-            const uint32_t off = (Q[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-            const uint32_t thr = *(const uint32_t *)(smem + th_base + off);
-            F = shift_in_less(F, wd[i], thr);
-        }
+        const u32x4 rw = philox4x32_10(8u * g + (uint32_t)q, c1, c2, d.sample_id, A.key0, A.key1);
+        const uint32_t Qq = Q[q];
+        F = shift_in_less(F, rw.w, lds_load(th_base + (Qq >> 24)));
+        F = shift_in_less(F, rw.z, lds_load(th_base + ((Qq >> 16) & 0xFFu)));
+        F = shift_in_less(F, rw.y, lds_load(th_base + ((Qq >> 8) & 0xFFu)));
+        F = shift_in_less(F, rw.x, lds_load(th_base + (Qq & 0xFFu)));
     }
     F |= D;
     own[g] = s ^ F;
@@ -284,7 +305,7 @@ __device__ __forceinline__ void run_bits_item(const SweepArgs &A, const SampleDe
         for (int i = tid; i < nT; i += T) I.sow[I.was[i]] = i;
         __syncthreads();
         const int t = on ? I.sow[w] : 0;
-        const uint32_t th_base = (uint32_t)(TH_OFF + 32 * t);
+        const uint32_t th_base = lds_addr(smem + TH_OFF + 32 * t);
         const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
         BitTally ty;
         if (on) {

@@ -434,8 +434,9 @@ bool down_is_threshold(uint32_t m)
     return k[0] + k[1] <= 8;  // the classes c < k_s then number at most 8
 }
 
-// The multispin engine is routed only once its GPU parity is established.
-constexpr bool kBitsEngine = false;
+// The multispin engine serves +-1 couplings at L = 8, 16, 32 unless a tier
+// option asks for the byte engines.
+constexpr bool kBitsEngine = true;
 
 int bits_threads(int L, int nT) { return ((nT * bits_tpw(L, nT) + 63) / 64) * 64; }
 

@@ -90,6 +90,7 @@ def test_pm1_couplings_lds_tier(torch_cuda):
     work = W.make_workload([8, 4, 6], 6, (0.5, 2.0), 0.4, jkind=W.J_PM1, measure_every=5,
                            measure_start=20, name="pm1")
     check(work, 150)
+    check(work, 40, tier=2)  # the byte engine at L = 8 too
 
 
 def test_degenerate_sizes(torch_cuda):
@@ -244,10 +245,43 @@ def test_autotune_keeps_results(torch_cuda):
     assert_same(work, st, ms, ref)
 
 
+# --- multispin (one bit per spin) engine, +-1 couplings at L = 8, 16, 32 -------
+def test_bits_engine_sizes_and_fields(torch_cuda):
+    # n_T = 1 (no exchange), odd n_T and lane groups that leave idle lanes;
+    # h = 0 (k_+ = k_- = 3), h = 0.4 and -0.3, |h| > 6 (one spin sign never
+    # lowers the energy, the other always does) and a tiny field
+    Ls = [8, 8, 16, 16, 32, 8, 16, 32, 8]
+    nT = [1, 5, 3, 24, 2, 17, 7, 3, 4]
+    hs = [0.0, 0.4, -0.3, 0.4, 0.4, 7.0, -6.5, 1e-3, 2.0]
+    work = W.make_workload(Ls, nT, (0.5, 2.0), hs, jkind=W.J_PM1, measure_every=3, measure_start=2,
+                           name="bits sizes/fields")
+    check(work, 25, plan=dict(chunk=9))
+
+
+def test_bits_engine_equals_byte_engines(torch_cuda):
+    work = W.make_workload([8, 16, 32], [6, 5, 4], (0.5, 2.0), [0.4, 0.1, -0.2], jkind=W.J_PM1,
+                           measure_every=2, measure_start=0, name="bits vs bytes")
+    st_b, ms_b, bad_b = gpu_run(work, 14)
+    st_y, ms_y, bad_y = gpu_run(work, 14, tier=2)
+    assert bad_b == 0 and bad_y == 0
+    for s in range(work.n_samples):
+        assert np.array_equal(st_b["spins"][s], st_y["spins"][s])
+        assert np.array_equal(st_b["E"][s], st_y["E"][s])
+        assert np.array_equal(ms_b["acc"][s], ms_y["acc"][s])
+        assert np.array_equal(ms_b["flips"][s], ms_y["flips"][s])
+
+
+def test_bits_engine_unbatched_and_resume(torch_cuda):
+    work = W.make_workload([32, 16], [4, 6], (0.5, 2.0), 0.4, jkind=W.J_PM1, sample_ids=[9, 3],
+                           measure_every=4, measure_start=1, name="bits unbatched")
+    check(work, 11, unbatched=True)
+    check(work, 11, splits=[4, 7], plan=dict(chunk=3))
+
+
 # --- HBM-resident tier --------------------------------------------------------
 def test_hbm_L32_pm1_subset(torch_cuda):
     work = W.config_workload("L32_pm1", samples=[0, 511], measure_start=0, measure_every=5)
-    check(work, 16)
+    check(work, 16, tier=1)
 
 
 def test_hbm_forced_gaussian_L8_L16(torch_cuda):
@@ -271,7 +305,7 @@ def test_hbm_mixed_tiers_pm1(torch_cuda):
 def test_hbm_unbatched_equals_oracle(torch_cuda):
     work = W.make_workload([32, 32], 4, (0.5, 2.0), 0.4, jkind=W.J_PM1, sample_ids=[5, 6], measure_every=3,
                            measure_start=0, name="pm1 unbatched")
-    check(work, 9, unbatched=True)
+    check(work, 9, unbatched=True, tier=1)
 
 
 def test_full_L32_workload_sampled(torch_cuda):
