@@ -752,13 +752,51 @@ EA_HBM(32)
 // plane sums are P_f[c] = 2 count - L^2 and
 // q(k_f) = sum_c P_f[c] e^{2 pi i c / L} / N (summed in c order), added to the
 // binary64 accumulators of the slot in time order.
+//
+// C and D come from bit-sliced vertical counters: lane y (C) adds the rows
+// (y, z) over z, lane 32 + z (D) the rows (y, z) over y, one 32-bit word per
+// step into six bit planes, and then reads the L column counts off the
+// planes.  Tables in LDS use a row stride of L + 1 words, so that the strided
+// reads of the plane sums fall in distinct banks.
+template <int L>
+__device__ __forceinline__ void column_counts(const uint32_t *eqr, int lane, int *C, int *D)
+{
+    constexpr int LP = L + 1;
+    const bool isC = lane < L, isD = lane >= 32 && lane - 32 < L;
+    if (!isC && !isD) return;
+    const int u = isC ? lane : lane - 32;
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
+#pragma unroll 4
+    for (int v = 0; v < L; ++v) {
+        const uint32_t w = eqr[isC ? u + LP * v : v + LP * u];
+        uint32_t k = c0 & w;
+        c0 ^= w;
+        uint32_t k2 = c1 & k;
+        c1 ^= k;
+        k = c2 & k2;
+        c2 ^= k2;
+        k2 = c3 & k;
+        c3 ^= k;
+        k = c4 & k2;
+        c4 ^= k2;
+        c5 |= k;  // counts reach at most L <= 32
+    }
+    int *dst = isC ? C : D;
+#pragma unroll
+    for (int x = 0; x < L; ++x) {
+        const int cnt = (int)(((c0 >> x) & 1u) | (((c1 >> x) & 1u) << 1) | (((c2 >> x) & 1u) << 2) |
+                              (((c3 >> x) & 1u) << 3) | (((c4 >> x) & 1u) << 4) | (((c5 >> x) & 1u) << 5));
+        dst[x * LP + u] = cnt;
+    }
+}
+
 template <int L>
 __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
 {
-    constexpr int L2 = L * L;
+    constexpr int L2 = L * L, LP = L + 1;
     constexpr uint32_t mask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
-    __shared__ uint32_t eqr[L2];
-    __shared__ int C[L2], D[L2], R[L2];
+    __shared__ uint32_t eqr[L * LP];
+    __shared__ int C[L * LP], D[L * LP], R[L * LP];
     __shared__ int P[NPLANE][L];
     __shared__ double accs[NACC];
     __shared__ double re_f[NPLANE], im_f[NPLANE];
@@ -783,20 +821,12 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
         const uint32_t *rb = ra + (size_t)d.n_T * L2;
         for (int i = tid; i < L2; i += T) {
             const uint32_t e = ~(ra[i] ^ rb[i]) & mask;
-            eqr[i] = e;
-            R[i] = __builtin_popcount(e);
+            const int y = i % L, z = i / L;
+            eqr[y + LP * z] = e;
+            R[y + LP * z] = __builtin_popcount(e);
         }
         __syncthreads();
-        // C[x][y] = #{z : e(x,y,z)},  D[x][z] = #{y : e(x,y,z)}
-        for (int e = tid; e < 2 * L2; e += T) {
-            const bool isC = e < L2;
-            const int e2 = isC ? e : e - L2;
-            const int x = e2 / L, u = e2 - x * L;
-            int cnt = 0;
-#pragma unroll
-            for (int v = 0; v < L; ++v) cnt += (eqr[isC ? u + L * v : v + L * u] >> x) & 1u;
-            (isC ? C : D)[e2] = cnt;
-        }
+        column_counts<L>(eqr, tid, C, D);  // C[x][y] at x*LP + y, D[x][z] at x*LP + z
         __syncthreads();
         for (int task = tid; task < NPLANE * L; task += T) {
             const int fam = task / L, c = task - fam * L;
@@ -807,15 +837,15 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
                 const int cp = c + v >= L ? c + v - L : c + v;   // c + v mod L
                 const int vm = v - c < 0 ? v - c + L : v - c;    // v - c mod L
                 switch (fam) {
-                case 0: cnt += C[c * L + v]; break;   // x = c
-                case 1: cnt += C[v * L + c]; break;   // y = c
-                case 2: cnt += D[v * L + c]; break;   // z = c
-                case 3: cnt += C[cm * L + v]; break;  // x + y = c
-                case 4: cnt += C[cp * L + v]; break;  // x - y = c
-                case 5: cnt += D[cm * L + v]; break;  // x + z = c
-                case 6: cnt += D[cp * L + v]; break;  // x - z = c
-                case 7: cnt += R[v + L * cm]; break;  // y + z = c
-                default: cnt += R[v + L * vm]; break; // y - z = c
+                case 0: cnt += C[c * LP + v]; break;   // x = c
+                case 1: cnt += C[v * LP + c]; break;   // y = c
+                case 2: cnt += D[v * LP + c]; break;   // z = c
+                case 3: cnt += C[cm * LP + v]; break;  // x + y = c
+                case 4: cnt += C[cp * LP + v]; break;  // x - y = c
+                case 5: cnt += D[cm * LP + v]; break;  // x + z = c
+                case 6: cnt += D[cp * LP + v]; break;  // x - z = c
+                case 7: cnt += R[v + LP * cm]; break;  // y + z = c
+                default: cnt += R[v + LP * vm]; break; // y - z = c
                 }
             }
             P[fam][c] = 2 * cnt - L2;
