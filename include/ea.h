@@ -188,6 +188,17 @@ enum {
 };
 ea_status ea_finalize(ea_ensemble *ens, int32_t L, int32_t n_temps, double *out_host);
 
+/* The same observables with their statistical errors from the disorder
+ * average (Methods: the error is dominated by the finite number of
+ * realizations): leave-one-sample-out jackknife over the samples with lattice
+ * size L and n_T slots, on the device.  out_mean and out_err [n_T][EA_NOBS]
+ * binary64 (caller-owned); out_mean is the full-sample estimate, out_err the
+ * jackknife standard error (0 in the EA_OBS_NSAMP column).  The sample sums
+ * are taken in a reduction tree, so out_mean may differ from ea_finalize in
+ * the last bits.  EA_EINVAL if fewer than two samples match.  Synchronizing. */
+ea_status ea_finalize_jackknife(ea_ensemble *ens, int32_t L, int32_t n_temps, double *out_mean,
+                                double *out_err);
+
 /* Launch plan (see ea_plan); EA_EINVAL for values out of range. */
 ea_status ea_set_plan(ea_ensemble *ens, const ea_plan *plan);
 ea_status ea_get_plan(const ea_ensemble *ens, ea_plan *plan);

@@ -66,6 +66,7 @@ _SIGS = [
     ("ea_reset_accumulators", ctypes.c_int, [_VP]),
     ("ea_check_energies", ctypes.c_int, [_VP, _VP]),
     ("ea_finalize", ctypes.c_int, [_VP, _I32, _I32, _VP]),
+    ("ea_finalize_jackknife", ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
     ("ea_set_plan", ctypes.c_int, [_VP, ctypes.POINTER(Plan)]),
     ("ea_get_plan", ctypes.c_int, [_VP, ctypes.POINTER(Plan)]),
     ("ea_autotune", ctypes.c_int, [_VP, _I32]),
@@ -236,6 +237,14 @@ class Ensemble:
         _check(load().ea_finalize(self._h, int(L), int(n_temps), _p(out)))
         out = out.reshape(n_temps, NOBS)
         return {k: out[:, i] for i, k in enumerate(OBS_NAMES)}
+
+    def finalize_jackknife(self, L: int, n_temps: int) -> dict:
+        """{observable: (value per slot, jackknife error per slot)}."""
+        m = np.zeros(n_temps * NOBS, dtype=np.float64)
+        e = np.zeros(n_temps * NOBS, dtype=np.float64)
+        _check(load().ea_finalize_jackknife(self._h, int(L), int(n_temps), _p(m), _p(e)))
+        m, e = m.reshape(n_temps, NOBS), e.reshape(n_temps, NOBS)
+        return {k: (m[:, i], e[:, i]) for i, k in enumerate(OBS_NAMES)}
 
     # -- planning and timing -------------------------------------------------
     def set_plan(self, chunk=None, threads=None, use_graph=None):

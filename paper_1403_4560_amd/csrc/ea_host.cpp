@@ -36,6 +36,7 @@ __global__ void energy_kernel(const SampleDev *, const int32_t *, const int8_t *
 __global__ void snapshot_kernel(const SampleDev *, const int32_t *, const int8_t *, const int32_t *,
                                 const int64_t *, const int32_t *, int, uint32_t *, double *);
 __global__ void finalize_kernel(const SampleDev *, int, int, int, const double *, double *);
+__global__ void finalize_jk_kernel(const SampleDev *, int, int, int, const double *, double *, double *);
 }  // namespace ea
 
 using namespace ea;
@@ -844,7 +845,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     ALLOC(slot_sample, sizeof(int32_t) * TS);
     ALLOC(costab, sizeof(double) * costab.size());
     ALLOC(sintab, sizeof(double) * sintab.size());
-    ALLOC(finout, sizeof(double) * MAX_T * EA_NOBS);
+    ALLOC(finout, sizeof(double) * 2 * MAX_T * EA_NOBS);
     ALLOC(dEJ, sizeof(int64_t) * 2 * TS);
     ALLOC(dM, sizeof(int32_t) * 2 * TS);
     ALLOC(sow, sizeof(int32_t) * 2 * TS);
@@ -1083,6 +1084,25 @@ ea_status ea_finalize(ea_ensemble *e, int32_t L, int32_t nT, double *out)
                        (const double *)e->acc.p, (double *)e->finout.p);
     HIP_TRY(e, hipGetLastError());
     HIP_TRY(e, hipMemcpyAsync(out, e->finout.p, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    return EA_OK;
+}
+
+ea_status ea_finalize_jackknife(ea_ensemble *e, int32_t L, int32_t nT, double *out_mean, double *out_err)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (!out_mean || !out_err) return fail(EA_EINVAL, "output is NULL");
+    if (nT < 1 || nT > MAX_T) return fail(EA_EINVAL, "n_temps out of range");
+    int matches = 0;
+    for (const auto &h : e->smp) matches += (h.L == L && h.nT == nT);
+    if (matches < 2) return fail(EA_EINVAL, "%d samples with L=%d and %d temperatures; the jackknife needs two",
+                                 matches, L, nT);
+    double *dm = (double *)e->finout.p, *de = dm + (size_t)MAX_T * EA_NOBS;
+    hipLaunchKernelGGL(finalize_jk_kernel, dim3(nT), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p, e->S,
+                       L, nT, (const double *)e->acc.p, dm, de);
+    HIP_TRY(e, hipGetLastError());
+    HIP_TRY(e, hipMemcpyAsync(out_mean, dm, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(out_err, de, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
     HIP_TRY(e, hipStreamSynchronize(e->stream));
     return EA_OK;
 }

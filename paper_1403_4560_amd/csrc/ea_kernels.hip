@@ -1034,28 +1034,10 @@ __global__ void __launch_bounds__(256) snapshot_kernel(const SampleDev *samples,
     }
 }
 
-// Disorder averages per slot over the samples of one lattice size and ladder
-// length (eqs. 3-6).  Single workgroup; thread t handles slot t and sums over
-// samples in sample order.
-__global__ void finalize_kernel(const SampleDev *samples, int S, int L, int nT, const double *acc,
-                                double *out)
+// Observables of eqs. 3-6 from disorder-averaged thermal means D[36] (column
+// order of ea_obs, without the sample count).
+__device__ __forceinline__ void observables_of(const double *D, int L, double *o)
 {
-    const int t = threadIdx.x;
-    if (t >= nT) return;
-    double D[NACC];
-    for (int j = 0; j < NACC; ++j) D[j] = 0.0;
-    int cnt = 0;
-    for (int s = 0; s < S; ++s) {
-        const SampleDev d = samples[s];
-        if (d.L != L || d.n_T != nT) continue;
-        const double *a = acc + ((size_t)d.slot_off + t) * NACC;
-        for (int j = 0; j < NACC; ++j) D[j] += a[j] / a[0];
-        ++cnt;
-    }
-    double *o = out + (size_t)t * 11;
-    o[10] = (double)cnt;
-    if (cnt == 0) return;
-    for (int j = 0; j < NACC; ++j) D[j] /= (double)cnt;
     const double N = (double)L * L * L;
     const double q1 = D[1], q2 = D[2], q3 = D[3], q4 = D[4], Q = q1;
     const double c2 = q2 - 2.0 * Q * q1 + Q * Q;
@@ -1078,6 +1060,116 @@ __global__ void finalize_kernel(const SampleDev *samples, int S, int L, int nT, 
     o[7] = chi0 / chik;
     o[8] = D[32];
     o[9] = D[34];
+}
+
+// Disorder averages per slot over the samples of one lattice size and ladder
+// length (eqs. 3-6).  Single workgroup; thread t handles slot t and sums over
+// samples in sample order.
+__global__ void finalize_kernel(const SampleDev *samples, int S, int L, int nT, const double *acc,
+                                double *out)
+{
+    const int t = threadIdx.x;
+    if (t >= nT) return;
+    double D[NACC];
+    for (int j = 0; j < NACC; ++j) D[j] = 0.0;
+    int cnt = 0;
+    for (int s = 0; s < S; ++s) {
+        const SampleDev d = samples[s];
+        if (d.L != L || d.n_T != nT) continue;
+        const double *a = acc + ((size_t)d.slot_off + t) * NACC;
+        for (int j = 0; j < NACC; ++j) D[j] += a[j] / a[0];
+        ++cnt;
+    }
+    double *o = out + (size_t)t * 11;
+    o[10] = (double)cnt;
+    if (cnt == 0) return;
+    for (int j = 0; j < NACC; ++j) D[j] /= (double)cnt;
+    observables_of(D, L, o);
+}
+
+// Leave-one-sample-out jackknife of the same observables (the statistical
+// error comes from the disorder average).  One workgroup per slot; threads
+// stride over samples.  With M = sum of the per-sample thermal means over the
+// cnt matching samples, replicate s uses (M - m_s) / (cnt - 1); the error is
+// sqrt((cnt - 1)/cnt sum_s (O_s - mean_s O_s)^2), two passes.  The central
+// value is the full-sample estimate M / cnt.
+__device__ __forceinline__ double block_sum_f64(double v, double *red)
+{
+    const int tid = threadIdx.x, T = blockDim.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int w = T / 2; w >= 1; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(256) finalize_jk_kernel(const SampleDev *samples, int S, int L, int nT,
+                                                          const double *acc, double *mean_out, double *err_out)
+{
+    __shared__ double red[256];
+    __shared__ double Msum[NACC];
+    __shared__ double Obar[10];
+    const int t = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
+    double part[NACC];
+    for (int j = 0; j < NACC; ++j) part[j] = 0.0;
+    int cnt = 0;
+    for (int s = tid; s < S; s += T) {
+        const SampleDev d = samples[s];
+        if (d.L != L || d.n_T != nT) continue;
+        const double *a = acc + ((size_t)d.slot_off + t) * NACC;
+        for (int j = 0; j < NACC; ++j) part[j] += a[j] / a[0];
+        ++cnt;
+    }
+    for (int j = 0; j < NACC; ++j) {
+        const double v = block_sum_f64(part[j], red);
+        if (tid == 0) Msum[j] = v;
+    }
+    const int total = (int)block_sum_f64((double)cnt, red);
+    __syncthreads();
+    if (total < 2) {
+        if (tid == 0)
+            for (int k = 0; k < 11; ++k) {
+                mean_out[(size_t)t * 11 + k] = k == 10 ? (double)total : 0.0;
+                err_out[(size_t)t * 11 + k] = 0.0;
+            }
+        return;
+    }
+    if (tid == 0) {
+        double D[NACC], o[10];
+        for (int j = 0; j < NACC; ++j) D[j] = Msum[j] / (double)total;
+        observables_of(D, L, o);
+        for (int k = 0; k < 10; ++k) mean_out[(size_t)t * 11 + k] = o[k];
+        mean_out[(size_t)t * 11 + 10] = (double)total;
+        err_out[(size_t)t * 11 + 10] = 0.0;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        double acc_o[10];
+        for (int k = 0; k < 10; ++k) acc_o[k] = 0.0;
+        for (int s = tid; s < S; s += T) {
+            const SampleDev d = samples[s];
+            if (d.L != L || d.n_T != nT) continue;
+            const double *a = acc + ((size_t)d.slot_off + t) * NACC;
+            double D[NACC], o[10];
+            for (int j = 0; j < NACC; ++j) D[j] = (Msum[j] - a[j] / a[0]) / (double)(total - 1);
+            observables_of(D, L, o);
+            for (int k = 0; k < 10; ++k) {
+                const double dv = pass == 0 ? o[k] : o[k] - Obar[k];
+                acc_o[k] += pass == 0 ? dv : dv * dv;
+            }
+        }
+        for (int k = 0; k < 10; ++k) {
+            const double v = block_sum_f64(acc_o[k], red);
+            if (tid == 0) {
+                if (pass == 0) Obar[k] = v / (double)total;
+                else err_out[(size_t)t * 11 + k] = sqrt((double)(total - 1) / (double)total * v);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace ea

@@ -30,7 +30,12 @@ JMAX_UNITS = 2 ** 21 - 1
 
 
 def geometric_betas(n_T: int, t_min: float, t_max: float) -> np.ndarray:
-    b_min, b_max = 1.0 / t_max, 1.0 / t_min
+    return beta_ladder(n_T, 1.0 / t_max, 1.0 / t_min)
+
+
+def beta_ladder(n_T: int, b_min: float, b_max: float) -> np.ndarray:
+    """beta_n = beta_min alpha^n, alpha = (beta_max/beta_min)^(1/(n_T-1)),
+    n = 0 .. n_T-1 (Table I caption)."""
     if n_T == 1:
         return np.array([b_min], dtype=np.float64)
     alpha = (b_max / b_min) ** (1.0 / (n_T - 1))
@@ -115,8 +120,9 @@ class Workload:
 
 
 def make_workload(Ls, n_temps, t_range, hs, jkind=J_GAUSS, seed=1, sample_ids=None,
-                  measure_every=10, measure_start=0, name="", sweeps=0) -> Workload:
-    """Per-sample lists (or scalars broadcast to S = len(Ls))."""
+                  measure_every=10, measure_start=0, name="", sweeps=0, beta_range=None) -> Workload:
+    """Per-sample lists (or scalars broadcast to S = len(Ls)).  The ladder is
+    geometric in beta over T in t_range, or over beta in beta_range if given."""
     S = len(Ls)
     n_temps = np.broadcast_to(np.asarray(n_temps, dtype=np.int32), (S,)).copy()
     hs = np.broadcast_to(np.asarray(hs, dtype=np.float32), (S,)).copy()
@@ -125,7 +131,7 @@ def make_workload(Ls, n_temps, t_range, hs, jkind=J_GAUSS, seed=1, sample_ids=No
     betas, Js, sp = [], [], []
     for s in range(S):
         L, nT, sid = int(Ls[s]), int(n_temps[s]), int(ids[s])
-        betas.append(geometric_betas(nT, *t_range))
+        betas.append(beta_ladder(nT, *beta_range) if beta_range is not None else geometric_betas(nT, *t_range))
         if jkind == J_GAUSS:
             Js.append(gaussian_couplings(seed, sid, L).ravel())
         else:
