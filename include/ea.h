@@ -95,10 +95,12 @@ typedef struct {
                                     EA_TIER_HBM: every sample whose L is
                                     divisible by 8 runs HBM-resident;
                                     EA_TIER_BYTES: as AUTO without the
-                                    one-bit engine.  Results are identical. */
+                                    one-bit engine; EA_TIER_SITE: every
+                                    LDS-resident sample on the one-site-per-
+                                    thread engine.  Results are identical. */
 } ea_desc;
 
-enum { EA_TIER_AUTO = 0, EA_TIER_HBM = 1, EA_TIER_BYTES = 2 };
+enum { EA_TIER_AUTO = 0, EA_TIER_HBM = 1, EA_TIER_BYTES = 2, EA_TIER_SITE = 3 };
 
 /* Launch plan.  Every plan gives bit-identical results. */
 typedef struct {

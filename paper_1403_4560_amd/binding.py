@@ -112,7 +112,7 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-TIER_AUTO, TIER_HBM, TIER_BYTES = 0, 1, 2
+TIER_AUTO, TIER_HBM, TIER_BYTES, TIER_SITE = 0, 1, 2, 3
 
 
 class Ensemble:
@@ -121,7 +121,8 @@ class Ensemble:
     ``work`` is a ``workload.Workload``; ``stream`` a raw HIP stream handle
     (e.g. ``torch.cuda.current_stream().cuda_stream``) or None for a stream
     owned by the ensemble; ``tier`` one of TIER_AUTO, TIER_HBM (samples with L
-    divisible by 8 HBM-resident) or TIER_BYTES (no one-bit engine)."""
+    divisible by 8 HBM-resident), TIER_BYTES (no one-bit engine) or TIER_SITE
+    (the one-site-per-thread engine for every LDS-resident sample)."""
 
     def __init__(self, work, stream=None, tier=0):
         lib = load()

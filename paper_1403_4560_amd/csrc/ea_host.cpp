@@ -24,6 +24,7 @@ namespace ea {
 template <int L, int JK, int VAR> __global__ void site_sweep_kernel(SweepArgs A);
 template <int L, int VAR> __global__ void row_sweep_kernel(SweepArgs A);
 template <int L, int VAR> __global__ void bits_sweep_kernel(SweepArgs A);
+template <int L, int JK, int VAR> __global__ void group_sweep_kernel(SweepArgs A);
 template <int L, int JK, int VAR> __global__ void hbm_half_kernel(SweepArgs A);
 __global__ void hbm_exchange_kernel(SweepArgs A);
 __global__ void hbm_snapshot_kernel(SweepArgs A);
@@ -64,6 +65,7 @@ struct SampleHost {
     int32_t slot_off;
     bool hbm;
     bool bits;       // multispin engine (+-1 couplings)
+    bool group;      // walker-interleaved engine
     int64_t jb_off;  // words into Jbits
 };
 
@@ -100,6 +102,7 @@ struct ea_ensemble {
         bool hbm;
         int wbegin, wcount;  // HBM tier: range of the walker table
         bool bits;           // multispin engine
+        bool group;          // walker-interleaved engine
     };
     std::vector<Class> classes;
     std::vector<int> item_pos;  // sample -> index of its chain-a item in the sorted item list
@@ -373,8 +376,21 @@ SweepFn site_fn(int L, int jk)
 #undef EA_CASE
 }
 
-SweepFn sweep_fn(int L, int jk, bool row, bool bits, bool unbatched)
+template <int VAR>
+SweepFn group_fn(int L, int jk)
 {
+#define EA_CASE(Lv) \
+    case Lv: return jk == 0 ? group_sweep_kernel<Lv, 0, VAR> : group_sweep_kernel<Lv, 1, VAR>;
+    switch (L) {
+        EA_CASE(2) EA_CASE(4) EA_CASE(6) EA_CASE(8) EA_CASE(10) EA_CASE(12) EA_CASE(14) EA_CASE(16)
+    default: return nullptr;
+    }
+#undef EA_CASE
+}
+
+SweepFn sweep_fn(int L, int jk, bool row, bool bits, bool group, bool unbatched)
+{
+    if (group) return unbatched ? group_fn<1>(L, jk) : group_fn<0>(L, jk);
     if (bits) {
         if (L == 8) return unbatched ? bits_sweep_kernel<8, 1> : bits_sweep_kernel<8, 0>;
         if (L == 16) return unbatched ? bits_sweep_kernel<16, 1> : bits_sweep_kernel<16, 0>;
@@ -441,6 +457,14 @@ constexpr bool kBitsEngine = true;
 
 int bits_threads(int L, int nT) { return ((nT * bits_tpw(L, nT) + 63) / 64) * 64; }
 
+// Group engine: one thread per (quad, group of four sites) up to
+// GROUP_MAX_THREADS; the launch takes the smaller of this and the plan's size.
+int group_threads(int L, int nT)
+{
+    const int items = ((nT + 3) / 4) * (L * L * L / 8);
+    return std::min(GROUP_MAX_THREADS, ((items + 63) / 64) * 64);
+}
+
 bool bits_engine(int L, int nT, int jk, float h, size_t lds_max)
 {
     if (!kBitsEngine) return false;
@@ -490,9 +514,10 @@ hipError_t launch_hbm_sweep(ea_ensemble *e, int L, int it, int item_first, int n
 hipError_t launch_class(ea_ensemble *e, const ea_ensemble::Class &c, int K, int first, int n_items, bool unbatched)
 {
     SweepArgs A = sweep_args(e, K, (const int32_t *)e->items.p + first, n_items);
-    SweepFn fn = sweep_fn(c.L, e->jkind, c.row, c.bits, unbatched);
+    SweepFn fn = sweep_fn(c.L, e->jkind, c.row, c.bits, c.group, unbatched);
     if (!fn) return hipErrorInvalidDeviceFunction;
-    const int threads = c.row || c.bits ? c.threads : e->plan.threads;
+    const int threads = c.row || c.bits ? c.threads : c.group ? std::min(c.threads, e->plan.threads)
+                                                              : e->plan.threads;
     hipLaunchKernelGGL(fn, dim3(n_items), dim3(threads), c.lds, e->stream, A);
     return hipGetLastError();
 }
@@ -628,8 +653,11 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         const size_t need = lds_offsets(h.L, h.nT, e->jkind).total;
         const bool fits = h.L <= LDS_MAX_L && need <= lds_max;
         const bool forced_hbm = d->tier == EA_TIER_HBM && hbm_size(h.L);
-        h.bits = !forced_hbm && d->tier != EA_TIER_BYTES && bits_engine(h.L, h.nT, e->jkind, h.h, lds_max);
+        h.bits = !forced_hbm && d->tier != EA_TIER_BYTES && d->tier != EA_TIER_SITE &&
+                 bits_engine(h.L, h.nT, e->jkind, h.h, lds_max);
         h.hbm = !h.bits && (!fits || forced_hbm);
+        h.group = !h.hbm && !h.bits && d->tier != EA_TIER_SITE && !row_engine(h.L, h.nT, e->jkind) &&
+                  h.L <= LDS_MAX_L && group_lds_offsets(h.L, h.nT, e->jkind).total <= lds_max;
         if (h.hbm && !hbm_size(h.L)) {
             destroy_all(e);
             return fail(EA_EUNSUPPORTED,
@@ -665,6 +693,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
             const SampleHost &x = e->smp[a], &y = e->smp[b];
             if (x.hbm != y.hbm) return y.hbm;
             if (x.bits != y.bits) return y.bits;
+            if (x.group != y.group) return y.group;
             return x.L < y.L;
         });
         e->item_pos.assign(e->S, 0);
@@ -674,8 +703,9 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         for (int i = 0; i < e->S; ++i) {
             const SampleHost &h = e->smp[order[i]];
             if (e->classes.empty() || e->classes.back().L != h.L || e->classes.back().hbm != h.hbm ||
-                e->classes.back().bits != h.bits)
-                e->classes.push_back({h.L, 2 * i, 0, 0, !h.hbm && !h.bits, 0, h.hbm, wtotal, 0, h.bits});
+                e->classes.back().bits != h.bits || e->classes.back().group != h.group)
+                e->classes.push_back(
+                    {h.L, 2 * i, 0, 0, !h.hbm && !h.bits && !h.group, 0, h.hbm, wtotal, 0, h.bits, h.group});
             ea_ensemble::Class &c = e->classes.back();
             c.count += 2;
             if (h.hbm) {
@@ -686,10 +716,14 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
             if (h.bits) {
                 c.lds = std::max(c.lds, bits_lds_offsets(h.L, h.nT).total);
                 c.threads = std::max(c.threads, bits_threads(h.L, h.nT));
+            } else if (h.group) {
+                c.lds = std::max(c.lds, group_lds_offsets(h.L, h.nT, e->jkind).total);
+                c.threads = std::max(c.threads, group_threads(h.L, h.nT));
             } else {
                 c.lds = std::max(c.lds, lds_offsets(h.L, h.nT, e->jkind).total);
-                c.row = c.row && row_engine(h.L, h.nT, e->jkind);
-                if (row_engine(h.L, h.nT, e->jkind)) c.threads = std::max(c.threads, row_threads(h.L, h.nT));
+                const bool row = d->tier != EA_TIER_SITE && row_engine(h.L, h.nT, e->jkind);
+                c.row = c.row && row;
+                if (row) c.threads = std::max(c.threads, row_threads(h.L, h.nT));
             }
             e->item_pos[order[i]] = 2 * i;
             e->sample_class[order[i]] = (int)e->classes.size() - 1;
@@ -697,7 +731,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         for (const auto &c : e->classes) {
             if (c.hbm) continue;
             for (int v = 0; v < 2; ++v) {
-                SweepFn fn = sweep_fn(c.L, e->jkind, c.row, c.bits, v == 1);
+                SweepFn fn = sweep_fn(c.L, e->jkind, c.row, c.bits, c.group, v == 1);
                 if (fn) (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                   (int)lds_max);
             }

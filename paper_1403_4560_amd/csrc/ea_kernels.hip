@@ -23,6 +23,7 @@
 #include "ea_device.hpp"
 #include "ea_item.hpp"
 #include "ea_types.hpp"
+#include "ea_update.hpp"
 
 namespace ea {
 
@@ -130,86 +131,6 @@ __device__ __forceinline__ void site_half_sweep(const SweepArgs &A, const Sample
     }
 }
 
-// ---------------------------------------------------------------------------
-// Metropolis update of one int8x4 word: four sites of one sublattice row with
-// their six neighbour words (aligned and shifted x, +y, -y, +z, -z; bytes +-1)
-// and their six bonds (int32 multiples of 2^-18).  rw holds the four Philox
-// words of the group, m2b = -2 beta32 of the walker's slot.  Returns the flip
-// mask (0xFE in the bytes of accepted sites).
-//
-// Energy tallies, by TALLY:
-//   TALLY_DELTA: accE += (S_u XOR m) over accepted sites, m = 0 for s_i = +1
-//     and -1 for s_i = -1, so that the sum of s_i S_u over accepted sites is
-//     accE + (accepted down spins);
-//   TALLY_NONE: nothing;
-//   TALLY_FINAL: accE += (S_u XOR m') over all four sites and nd += the number
-//     of -1 spins after the update, m' from the updated spin, so that
-//     accE + nd = sum of s_i' S_u with the updated spins s_i'.  On the second
-//     half-sweep this is the whole coupling energy: every bond joins one even
-//     and one odd site, and the even spins no longer change, so E_J of the
-//     walker is minus the sum of s_i' S_u over its odd sites.
-// S_u can reach 6 (2^21 - 1) in magnitude, beyond a 24-bit multiplier, so the
-// sign is applied by XOR.
-//
-// Decision: x = -fl32(beta32 dE) is formed as fl32((-2 beta32 s_i) f) (the same
-// real number, rounded once), dE <= 0 iff x >= 0, exp_ea32 is 0 below -86.  The
-// random word is decided by accept_bracket when it falls outside the bracket
-// (ea_verify_exp_bracket proves the bracket safe for every x <= 0, and that
-// below -86 no word falls under it), otherwise by U 2^-24 < exp_ea32(x)
-// itself.  For x >= 0 both routes accept, as the contract's dE <= 0 rule does.
-constexpr int TALLY_DELTA = 0, TALLY_NONE = 1, TALLY_FINAL = 2;
-
-template <int TALLY>
-__device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, uint32_t Xs, uint32_t Yp,
-                                                      uint32_t Ym, uint32_t Zp, uint32_t Zm, const int Ja[4],
-                                                      const int Js[4], const int Jy[4], const int Jyn[4],
-                                                      const int Jz[4], const int Jzn[4], const u32x4 rw,
-                                                      float m2b, float h32, int &accE, int &nd)
-{
-    const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
-    const uint32_t nS = ~Sv;                            // byte sign bit set iff s_i = +1
-    const uint32_t b2 = __float_as_uint(m2b) & 0x7FFFFFFFu;  // 2 beta32
-    uint32_t fm = 0;
-    int Sus[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int sh = 8 * i;
-        int Su = __mul24(__builtin_amdgcn_sbfe((int)Xa, sh, 8), Ja[i]);
-        Su += __mul24(__builtin_amdgcn_sbfe((int)Xs, sh, 8), Js[i]);
-        Su += __mul24(__builtin_amdgcn_sbfe((int)Yp, sh, 8), Jy[i]);
-        Su += __mul24(__builtin_amdgcn_sbfe((int)Ym, sh, 8), Jyn[i]);
-        Su += __mul24(__builtin_amdgcn_sbfe((int)Zp, sh, 8), Jz[i]);
-        Su += __mul24(__builtin_amdgcn_sbfe((int)Zm, sh, 8), Jzn[i]);
-        Sus[i] = Su;
-        // f = fl32(S_J + h): S_J = Su 2^-18 exactly, so the fused form rounds once, as the sum does
-        const float f = __builtin_fmaf((float)Su, 0x1p-18f, h32);
-        // c = -2 beta32 s_i: the sign bit of 2 beta32 set iff s_i = +1 (exact)
-        const float c = __uint_as_float(__builtin_amdgcn_ubfe(nS, sh + 7, 1) << 31 | b2);
-        const float x = c * f;                         // = -fl32(beta * dE)
-        float lo, hi;
-        accept_bracket(x, lo, hi);
-        const float Wf = (float)words[i];
-        const bool below = Wf < lo, under_hi = Wf < hi;  // lo < hi, so below implies under_hi
-        bool accept = below;
-        // If a lane of the wave has lo <= W < hi (the two lane masks differ),
-        // every lane takes the exact test, which the bracket only anticipates.
-        if (__builtin_amdgcn_ballot_w64(under_hi) != __builtin_amdgcn_ballot_w64(below))
-            accept = (float)(words[i] >> 8) * 0x1p-24f < exp_ea32(x);
-        fm |= accept ? 0xFEu << sh : 0u;
-        if constexpr (TALLY == TALLY_DELTA) {
-            const int m = __builtin_amdgcn_sbfe((int)Sv, sh + 7, 1);  // 0: s_i = +1, -1: s_i = -1
-            accE += accept ? (Su ^ m) : 0;
-        }
-    }
-    if constexpr (TALLY == TALLY_FINAL) {
-        const uint32_t Sn = Sv ^ fm;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) accE += Sus[i] ^ __builtin_amdgcn_sbfe((int)Sn, 8 * i + 7, 1);
-        nd += __builtin_popcount(Sn & 0x80808080u);
-    }
-    return fm;
-}
-
 // The same for +-1 couplings (int8x4 bond words Ja..Jzn): a bond-spin product
 // byte n ^ J is 0x00 for +1 and 0xFE for -1, so per byte c = number of -1
 // products and S_J = 6 - 2c.  Acceptance uses the slot's threshold table
@@ -252,7 +173,7 @@ __device__ __forceinline__ uint32_t update_word_pm1(uint32_t Sv, uint32_t Xa, ui
 //
 // Tallies per thread and sweep: the first half-sweep tallies no energy; the
 // second gives accE + nd = sum of s_i S_u over the thread's odd sites after
-// the update (TALLY_FINAL), i.e. minus its share of the walker's new E_J;
+// the update (tally_final), i.e. minus its share of the walker's new E_J;
 // bf and bd count the set bits of the flip masks (7 per flipped byte) and of
 // (spins AND flip mask) over both halves.
 //
@@ -305,8 +226,10 @@ __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d,
     const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
     const uint32_t g = (uint32_t)(o_y0 / 4 + z * (PLANE / 4));
     const u32x4 rw = philox4x32_10(g, c1, c2, d.sample_id, A.key0, A.key1);
-    const uint32_t fm = update_word_gauss<P == 0 ? TALLY_NONE : TALLY_FINAL>(
-        Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b, d.h32, accE, nd);
+    const float m2bv[4] = {m2b, m2b, m2b, m2b};
+    int Sus[4];
+    const uint32_t fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2bv, d.h32, Sus);
+    if constexpr (P == 1) tally_final(Sv, fm, Sus, accE, nd);
     *(uint32_t *)(Sw + P * HALF + o_y0 + zo) = Sv ^ fm;
     bf += __builtin_popcount(fm);
     bd += __builtin_popcount(Sv & fm);
@@ -621,9 +544,10 @@ __global__ void __launch_bounds__(256) hbm_half_kernel(SweepArgs A)
             const int Js[4] = {eps ? Jpx.x : Ep, eps ? Jpx.y : V.x, eps ? Jpx.z : V.y, eps ? Jpx.w : V.z};
             const int Jy[4] = {Jpy.x, Jpy.y, Jpy.z, Jpy.w}, Jyn[4] = {Jym.x, Jym.y, Jym.z, Jym.w};
             const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
-            int unused = 0;
-            fm = update_word_gauss<TALLY_DELTA>(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2b,
-                                                d.h32, accE, unused);
+            const float m2bv[4] = {m2b, m2b, m2b, m2b};
+            int Sus[4];
+            fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2bv, d.h32, Sus);
+            accE += tally_delta(Sv, fm, Sus);
         } else {
             const uint8_t *J8 = (const uint8_t *)A.J + d.J_off;
             const uint8_t *Jp = J8 + (size_t)p * 3 * HALF, *Jo = J8 + (size_t)(1 - p) * 3 * HALF;

@@ -36,6 +36,7 @@ constexpr int MAX_T = 64;     // temperature slots per sample
 constexpr int MAX_L = 32;     // a row of spins fits one 32-bit snapshot word
 constexpr int LDS_MAX_L = 16; // largest lattice of the LDS-resident tier
 constexpr int ROW_MAX_THREADS = 768;  // row engine: one thread per (walker, column)
+constexpr int GROUP_MAX_THREADS = 512;  // group engine workgroup size cap
 
 struct SampleDev {
     int32_t L;
@@ -171,6 +172,36 @@ __host__ __device__ inline BitsLdsOff bits_lds_offsets(int L, int nT)
     o.EJ = align16(o.sw + 4 * T4);
     o.dEJ = o.EJ + 8 * T4;
     o.b64 = o.dEJ + 8 * T4;
+    o.total = align16(o.b64 + 8 * T4);
+    return o;
+}
+
+// LDS layout of one group-engine work item (bytes): quad words
+// [2][4][N/8][ceil(n_T/4)], couplings (int32 units of 2^-18, or int8 +-1)
+// [2][3][N/2], +-1 threshold tables [n_T][14], then the per-walker/slot
+// arrays of the common frame.
+struct GroupLdsOff {
+    size_t spins, J, lut, was, sow, M, dM, fl, sw, EJ, dEJ, b32, b64, total;
+};
+
+__host__ __device__ inline GroupLdsOff group_lds_offsets(int L, int nT, int jkind)
+{
+    const size_t N = (size_t)L * L * L, NQ = (size_t)(nT + 3) / 4;
+    const size_t T4 = (size_t)((nT + 3) & ~3);
+    GroupLdsOff o;
+    o.spins = 0;
+    o.J = N * NQ * 4;
+    o.lut = align16(o.J + 3 * N * (jkind == 0 ? 4 : 1));
+    o.was = o.lut + (jkind == 1 ? 4 * 14 * T4 : 0);
+    o.sow = o.was + 4 * T4;
+    o.M = o.sow + 4 * T4;
+    o.dM = o.M + 4 * T4;
+    o.fl = o.dM + 4 * T4;
+    o.sw = o.fl + 4 * T4;
+    o.EJ = align16(o.sw + 4 * T4);
+    o.dEJ = o.EJ + 8 * T4;
+    o.b32 = o.dEJ + 8 * T4;
+    o.b64 = align16(o.b32 + 4 * T4);
     o.total = align16(o.b64 + 8 * T4);
     return o;
 }

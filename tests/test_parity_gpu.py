@@ -101,6 +101,32 @@ def test_degenerate_sizes(torch_cuda):
     check(work, 50)
 
 
+def test_site_engine_forced(torch_cuda):
+    # the one-site-per-thread engine (EA_TIER_SITE) for every LDS-resident size
+    work = W.make_workload([4, 6, 8, 10, 12, 16], [3, 5, 4, 2, 6, 3], (0.5, 2.0), [0.3, 0.1, 0.2, 0.0, 0.4, 0.1],
+                           measure_every=3, measure_start=2, name="site forced")
+    check(work, 20, tier=3, plan=dict(chunk=7))
+    pm1 = W.make_workload([4, 6, 8], 5, (0.5, 2.0), 0.4, jkind=W.J_PM1, measure_every=2, name="site forced pm1")
+    check(pm1, 20, tier=3)
+
+
+def test_group_engine_quads_and_fields(torch_cuda):
+    # walker-interleaved engine: partial quads (n_T = 1, 2, 3, 5, 7), full ones
+    # (4, 16), the Table I ladder length (56), both coupling kinds
+    work = W.make_workload([6, 10, 12, 14, 4, 2, 6], [1, 2, 3, 5, 7, 16, 56], (0.5, 2.0),
+                           [0.1, 0.3, -0.2, 0.0, 0.4, 0.2, 0.1], measure_every=4, measure_start=1,
+                           name="group quads")
+    check(work, 12, plan=dict(chunk=5))
+    pm1 = W.make_workload([6, 10, 4, 12], [56, 3, 5, 16], (0.5, 2.0), [0.1, 0.4, -0.3, 2.0], jkind=W.J_PM1,
+                          measure_every=3, name="group quads pm1")
+    check(pm1, 10, splits=[4, 6])
+
+
+def test_group_engine_unbatched(torch_cuda):
+    work = W.config_workload("mixed_L6_12", samples=[0, 2, 3], measure_start=4)
+    check(work, 16, unbatched=True)
+
+
 def test_never_measure(torch_cuda):
     work = W.make_workload([4, 6], 4, (0.5, 2.0), 0.3, measure_every=0, name="m0")
     st, ms, ref = check(work, 30)
