@@ -3,9 +3,10 @@
 // and the one-bit engine (+-1 L = 8, 16, 32) do not take.
 //
 // Layout: one int8x4 word holds one site of four walkers of a chain (a
-// "quad"), [2 parities][h & 3][h >> 2][quads] for sublattice site h, so that
-// the lanes of a wave, which take consecutive groups of four sites, read
-// consecutive words at each step; a site's six neighbour words and
+// "quad"), [2 parities][quads][N/2 + 1 sites] (the odd plane stride spreads
+// the quads of a wave over all LDS banks); a per-item table gives every
+// sublattice site its six neighbours in the other sublattice as 16-bit
+// indices (both checkerboard offsets for x); a site's six neighbour words and
 // six bonds serve four Metropolis attempts at once and the neighbour
 // arithmetic works for any L (the four sites of a Philox group may lie in
 // different rows).  A work item is (quad, group of four consecutive sublattice
@@ -45,8 +46,20 @@ __device__ __forceinline__ void group_nbrs(int p, int h, int nb[6])
 template <int L>
 __device__ __forceinline__ int gidx(int p, int h, int q, int NQ)
 {
-    constexpr int G4 = L * L * L / 8;
-    return ((p * 4 + (h & 3)) * G4 + (h >> 2)) * NQ + q;
+    constexpr int PS = L * L * L / 2 + 1;
+    return (p * NQ + q) * PS + h;
+}
+
+// Neighbour table entry of sublattice site h: {+y | -y << 16, +z | -z << 16,
+// +x | -x << 16 for parity 0, the same for parity 1}.
+template <int L>
+__device__ __forceinline__ uint4 nbr_entry(int h)
+{
+    int n0[6], n1[6];
+    group_nbrs<L>(0, h, n0);
+    group_nbrs<L>(1, h, n1);
+    return make_uint4((uint32_t)n0[2] | (uint32_t)n0[3] << 16, (uint32_t)n0[4] | (uint32_t)n0[5] << 16,
+                      (uint32_t)n0[0] | (uint32_t)n0[1] << 16, (uint32_t)n1[0] | (uint32_t)n1[1] << 16);
 }
 
 struct GroupLane {
@@ -66,22 +79,26 @@ struct GroupTally {
 // Metropolis update of work item (quad q, sites 4 g4 .. 4 g4 + 3) of parity P.
 template <int L, int JK, int P>
 __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &d, uint32_t *SG, const void *Jl,
-                                           const uint32_t *lut, int NQ, int q, int g4, uint32_t c1,
+                                           const uint32_t *lut, const uint4 *NB, int NQ, int q, int g4, uint32_t c1,
                                            const GroupLane &ln, GroupTally &ty)
 {
-    constexpr int HALF = L * L * L / 2;
+    constexpr int HALF = L * L * L / 2, PS = HALF + 1;
+    uint32_t *Sp = SG + (P * NQ + q) * PS;
+    const uint32_t *So = SG + ((1 - P) * NQ + q) * PS;
     u32x4 rw[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) rw[i] = philox4x32_10((uint32_t)g4, c1, ln.c2[i], d.sample_id, A.key0, A.key1);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int h = 4 * g4 + k;
-        int nb[6];
-        group_nbrs<L>(P, h, nb);
-        const uint32_t Sv = SG[gidx<L>(P, h, q, NQ)];
+        const uint4 te = NB[h];
+        const uint32_t tx = P ? te.w : te.z;
+        const int nb[6] = {(int)(tx & 0xFFFFu), (int)(tx >> 16), (int)(te.x & 0xFFFFu), (int)(te.x >> 16),
+                           (int)(te.y & 0xFFFFu), (int)(te.y >> 16)};
+        const uint32_t Sv = Sp[h];
         uint32_t X[6];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) X[j] = SG[gidx<L>(1 - P, nb[j], q, NQ)];
+        for (int j = 0; j < 6; ++j) X[j] = So[nb[j]];
         const u32x4 rk = {k == 0 ? rw[0].x : k == 1 ? rw[0].y : k == 2 ? rw[0].z : rw[0].w,
                           k == 0 ? rw[1].x : k == 1 ? rw[1].y : k == 2 ? rw[1].z : rw[1].w,
                           k == 0 ? rw[2].x : k == 1 ? rw[2].y : k == 2 ? rw[2].z : rw[2].w,
@@ -123,7 +140,7 @@ __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &
             }
             fm &= ln.valid;
         }
-        SG[gidx<L>(P, h, q, NQ)] = Sv ^ fm;
+        Sp[h] = Sv ^ fm;
         ty.flips += (fm >> 7) & 0x01010101u;
         ty.fdown += ((fm & Sv) >> 7) & 0x01010101u;
         if constexpr (P == 1) {
@@ -145,6 +162,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     uint32_t *SG = (uint32_t *)(smem + o.spins);
     void *Jl = (void *)(smem + o.J);
     uint32_t *lut = (uint32_t *)(smem + o.lut);
+    uint4 *NB = (uint4 *)(smem + o.nb);
     ItemLds I{};
     I.was = (int32_t *)(smem + o.was);
     I.sow = (int32_t *)(smem + o.sow);
@@ -170,6 +188,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         }
         SG[gidx<L>(ph / HALF, ph % HALF, q, NQ)] = wv;
     }
+    for (int h = tid; h < HALF; h += T) NB[h] = nbr_entry<L>(h);
     if constexpr (JK == 0) {
         // couplings as exact int32 multiples of 2^-18
         const float *src = (const float *)A.J + d.J_off;
@@ -222,13 +241,13 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         if (on) {
             const uint32_t c1 = (uint32_t)(2 * n);
 #pragma unroll 1
-            for (int g4 = gs; g4 < G4; g4 += TPQ) group_item<L, JK, 0>(A, d, SG, Jl, lut, NQ, q, g4, c1, ln, ty);
+            for (int g4 = gs; g4 < G4; g4 += TPQ) group_item<L, JK, 0>(A, d, SG, Jl, lut, NB, NQ, q, g4, c1, ln, ty);
         }
         __syncthreads();
         if (on) {
             const uint32_t c1 = (uint32_t)(2 * n + 1);
 #pragma unroll 1
-            for (int g4 = gs; g4 < G4; g4 += TPQ) group_item<L, JK, 1>(A, d, SG, Jl, lut, NQ, q, g4, c1, ln, ty);
+            for (int g4 = gs; g4 < G4; g4 += TPQ) group_item<L, JK, 1>(A, d, SG, Jl, lut, NB, NQ, q, g4, c1, ln, ty);
             for (int i = 0; i < 4; ++i) {
                 const int w = 4 * q + i;
                 if (w >= nT) break;
@@ -292,7 +311,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
 
 // VAR only separates the symbol of the one-sample-per-launch comparator.
 template <int L, int JK, int VAR>
-__global__ void __launch_bounds__(GROUP_MAX_THREADS) group_sweep_kernel(SweepArgs A)
+__global__ void __launch_bounds__(GROUP_MAX_THREADS, 4) group_sweep_kernel(SweepArgs A)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {

@@ -177,11 +177,11 @@ __host__ __device__ inline BitsLdsOff bits_lds_offsets(int L, int nT)
 }
 
 // LDS layout of one group-engine work item (bytes): quad words
-// [2][4][N/8][ceil(n_T/4)], couplings (int32 units of 2^-18, or int8 +-1)
-// [2][3][N/2], +-1 threshold tables [n_T][14], then the per-walker/slot
-// arrays of the common frame.
+// [2][ceil(n_T/4)][N/2 + 1], couplings (int32 units of 2^-18, or int8 +-1)
+// [2][3][N/2], the neighbour table [N/2] (16 B per site), +-1 threshold
+// tables [n_T][14], then the per-walker/slot arrays of the common frame.
 struct GroupLdsOff {
-    size_t spins, J, lut, was, sow, M, dM, fl, sw, EJ, dEJ, b32, b64, total;
+    size_t spins, J, nb, lut, was, sow, M, dM, fl, sw, EJ, dEJ, b32, b64, total;
 };
 
 __host__ __device__ inline GroupLdsOff group_lds_offsets(int L, int nT, int jkind)
@@ -190,8 +190,9 @@ __host__ __device__ inline GroupLdsOff group_lds_offsets(int L, int nT, int jkin
     const size_t T4 = (size_t)((nT + 3) & ~3);
     GroupLdsOff o;
     o.spins = 0;
-    o.J = N * NQ * 4;
-    o.lut = align16(o.J + 3 * N * (jkind == 0 ? 4 : 1));
+    o.J = align16(2 * NQ * (N / 2 + 1) * 4);
+    o.nb = align16(o.J + 3 * N * (jkind == 0 ? 4 : 1));
+    o.lut = o.nb + (N / 2) * 16;
     o.was = o.lut + (jkind == 1 ? 4 * 14 * T4 : 0);
     o.sow = o.was + 4 * T4;
     o.M = o.sow + 4 * T4;
