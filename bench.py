@@ -67,6 +67,7 @@ WORKLOAD_TEXT = {
 #   unsatisfied-bond words (6), the count c (8), dE <= 0 (8), class planes
 #   (3), new spins (1), flip and down-flip counts (3), energy on the second
 #   half only (7, 3.5 on average) = 42.5: 474.5 / 32 = 14.83.
+BYTE_PM1_OPS_PER_ATTEMPT = 25.5
 ALG_OPS_PER_ATTEMPT = {"L16_gauss": 34.25, "L8_gauss": 34.25, "mixed_L6_12": 34.25, "L4_gauss": 34.25,
                        "L32_pm1": 474.5 / 32}
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = non-packed VALU lane-instructions/s.
@@ -126,6 +127,9 @@ def main():
     ap.add_argument("--no-unbatched", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="time candidate plans first (the L=16 row engine has no thread-count knob)")
+    ap.add_argument("--tier", type=int, default=0,
+                    help="0 automatic (default); 1 HBM-resident for L divisible by 8; 2 no one-bit engine; "
+                         "3 one-site-per-thread engine (comparisons only)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="before timing, run a plain device-to-device copy of this many bytes "
                          "(a reference kernel of known traffic for hardware byte counters)")
@@ -149,7 +153,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     work = W.config_workload(args.workload, measure_start=0, measure_every=10)
-    ens = binding.Ensemble(work, stream=stream.cuda_stream)
+    ens = binding.Ensemble(work, stream=stream.cuda_stream, tier=args.tier)
     ens.set_plan(chunk=SWEEPS_PER_STEP)
     plan = ens.autotune(trial_sweeps=4) if args.autotune else ens.get_plan()
     ens.set_plan(chunk=SWEEPS_PER_STEP)
@@ -176,19 +180,22 @@ def main():
     avg_launch_s = k_ms / 1e3 / max(k_launches, 1)
     attempts_per_launch = attempts_per_step  # one launch per step (chunk)
     ops = ALG_OPS_PER_ATTEMPT[args.workload]
-    fp, traffic = MEASURED_TRAFFIC.get(args.workload, (None, None))
+    if work.jkind == 1 and args.tier != 0:
+        ops = BYTE_PM1_OPS_PER_ATTEMPT  # +-1 couplings on the byte engines
+    fp, traffic = MEASURED_TRAFFIC.get(args.workload, (None, None)) if args.tier == 0 else (None, None)
     if fp != kernel_fingerprint():
         traffic = None
+    kernel = KERNEL.get(args.workload, "sweep kernels") if args.tier == 0 else "tier %d kernels" % args.tier
     achieved = attempts_per_launch * ops / avg_launch_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                 "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                "kernel": KERNEL.get(args.workload, "sweep kernels"), "avg_launch_ms": avg_launch_s * 1e3,
+                "kernel": kernel, "avg_launch_ms": avg_launch_s * 1e3,
                 "ops_per_attempt": ops, "traffic_unit": "HBM bytes per launch (hardware counters)"}
 
     unbatched = None
     if not args.no_unbatched:
         sub = work.subset(range(min(args.unbatched_samples, work.n_samples)))
-        ub = binding.Ensemble(sub, stream=stream.cuda_stream)
+        ub = binding.Ensemble(sub, stream=stream.cuda_stream, tier=args.tier)
         ub.set_plan(chunk=SWEEPS_PER_STEP, threads=plan.threads)
         ub.sweep_pt_unbatched(SWEEPS_PER_STEP)
         torch.cuda.synchronize()
@@ -217,6 +224,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "sweeps_per_step": SWEEPS_PER_STEP, "samples": work.n_samples,
                    "attempts_per_step": attempts_per_step, "threads_per_workgroup": plan.threads,
+                   "tier": args.tier,
                    "parallelism": "samples x chains across workgroups"},
         "unbatched": unbatched,
         "roofline": roofline,

@@ -459,11 +459,9 @@ int bits_threads(int L, int nT) { return ((nT * bits_tpw(L, nT) + 63) / 64) * 64
 
 // Group engine: one thread per (quad, group of four sites) up to
 // GROUP_MAX_THREADS; the launch takes the smaller of this and the plan's size.
-int group_threads(int L, int nT)
-{
-    const int items = ((nT + 3) / 4) * (L * L * L / 8);
-    return std::min(GROUP_MAX_THREADS, ((items + 63) / 64) * 64);
-}
+int group_items(int L, int nT) { return ((nT + 3) / 4) * (L * L * L / 8); }
+
+int group_threads(int L, int nT) { return std::min(GROUP_MAX_THREADS, ((group_items(L, nT) + 63) / 64) * 64); }
 
 bool bits_engine(int L, int nT, int jk, float h, size_t lds_max)
 {
@@ -656,8 +654,12 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         h.bits = !forced_hbm && d->tier != EA_TIER_BYTES && d->tier != EA_TIER_SITE &&
                  bits_engine(h.L, h.nT, e->jkind, h.h, lds_max);
         h.hbm = !h.bits && (!fits || forced_hbm);
+        // the group engine needs a wave's worth of (quad, site group) items;
+        // tinier chains (L = 2, 4) keep the one-site-per-thread engine, which
+        // spreads them over more lanes
         h.group = !h.hbm && !h.bits && d->tier != EA_TIER_SITE && !row_engine(h.L, h.nT, e->jkind) &&
-                  h.L <= LDS_MAX_L && group_lds_offsets(h.L, h.nT, e->jkind).total <= lds_max;
+                  h.L <= LDS_MAX_L && group_items(h.L, h.nT) >= 64 &&
+                  group_lds_offsets(h.L, h.nT, e->jkind).total <= lds_max;
         if (h.hbm && !hbm_size(h.L)) {
             destroy_all(e);
             return fail(EA_EUNSUPPORTED,

@@ -112,9 +112,10 @@ def test_site_engine_forced(torch_cuda):
 
 def test_group_engine_quads_and_fields(torch_cuda):
     # walker-interleaved engine: partial quads (n_T = 1, 2, 3, 5, 7), full ones
-    # (4, 16), the Table I ladder length (56), both coupling kinds
-    work = W.make_workload([6, 10, 12, 14, 4, 2, 6], [1, 2, 3, 5, 7, 16, 56], (0.5, 2.0),
-                           [0.1, 0.3, -0.2, 0.0, 0.4, 0.2, 0.1], measure_every=4, measure_start=1,
+    # (4, 16), the Table I ladder length (56), both coupling kinds; L = 4 with
+    # 32 temperatures has enough work items for it, L = 2 and 4 with few do not
+    work = W.make_workload([6, 10, 12, 14, 4, 2, 6, 4], [1, 2, 3, 5, 7, 16, 56, 32], (0.5, 2.0),
+                           [0.1, 0.3, -0.2, 0.0, 0.4, 0.2, 0.1, 0.3], measure_every=4, measure_start=1,
                            name="group quads")
     check(work, 12, plan=dict(chunk=5))
     pm1 = W.make_workload([6, 10, 4, 12], [56, 3, 5, 16], (0.5, 2.0), [0.1, 0.4, -0.3, 2.0], jkind=W.J_PM1,
