@@ -182,6 +182,7 @@ ea_status validate(const ea_desc *d)
     if (d->jkind != EA_J_GAUSS_F32 && d->jkind != EA_J_PM1_I8) return fail(EA_EINVAL, "unknown jkind %d", d->jkind);
     if (d->measure_every < 0) return fail(EA_EINVAL, "measure_every must be >= 0");
     if (d->measure_start < 0) return fail(EA_EINVAL, "measure_start must be >= 0");
+    if (d->tier < EA_TIER_AUTO || d->tier > EA_TIER_SITE) return fail(EA_EINVAL, "unknown tier %d", d->tier);
     int64_t boff = 0, joff = 0, soff = 0;
     for (int s = 0; s < d->n_samples; ++s) {
         const int L = d->L[s], nT = d->n_temps[s];

@@ -40,7 +40,7 @@ def _desc(work, **over):
     p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
     d = binding.Desc(len(arrs["L"]), p(arrs["sid"]), p(arrs["L"]), p(arrs["nT"]), p(arrs["beta"]),
                      p(arrs["h"]), int(over.get("jkind", work.jkind)), p(arrs["J"]), p(arrs["spins"]),
-                     1, int(over.get("m", 10)), int(over.get("start", 0)), 0)
+                     1, int(over.get("m", 10)), int(over.get("start", 0)), int(over.get("tier", 0)))
     return d, arrs
 
 
@@ -119,3 +119,9 @@ def test_null_handles_are_rejected():
     assert lib.ea_measure(None, 0, None, None, None) == -4
     assert lib.ea_create_ensemble(None, None, None) == -1
     lib.ea_destroy(None)
+
+
+def test_rejects_unknown_tier(small):
+    d, keep = _desc(small, tier=4)
+    st, h, msg = _create(d)
+    assert st == -1 and not h.value and "tier" in msg
