@@ -721,7 +721,9 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
     constexpr uint32_t mask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
     __shared__ uint32_t eqr[L * LP];
     __shared__ int C[L * LP], D[L * LP], R[L * LP];
+    constexpr int GC = 64 / L;  // chunks of v per plane count
     __shared__ int P[NPLANE][L];
+    __shared__ int part[NPLANE][GC][L];
     __shared__ double accs[NACC];
     __shared__ double re_f[NPLANE], im_f[NPLANE];
     const int gs = A.slots[blockIdx.x];
@@ -752,26 +754,36 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
         __syncthreads();
         column_counts<L>(eqr, tid, C, D);  // C[x][y] at x*LP + y, D[x][z] at x*LP + z
         __syncthreads();
+        // plane counts: lane (c, chunk) sums v = chunk, chunk + GC, ... of
+        // every family (no divergence: the family loop is unrolled), then
+        // (family, c) tasks add the GC chunk partials (integers: any order)
+        if (tid < L * GC) {
+            const int c = tid % L, chunk = tid / L;
+#pragma unroll
+            for (int fam = 0; fam < NPLANE; ++fam) {
+                int cnt = 0;
+                for (int v = chunk; v < L; v += GC) {
+                    const int cm = c - v < 0 ? c - v + L : c - v;    // c - v mod L
+                    const int cp = c + v >= L ? c + v - L : c + v;   // c + v mod L
+                    const int vm = v - c < 0 ? v - c + L : v - c;    // v - c mod L
+                    if (fam == 0) cnt += C[c * LP + v];        // x = c
+                    else if (fam == 1) cnt += C[v * LP + c];   // y = c
+                    else if (fam == 2) cnt += D[v * LP + c];   // z = c
+                    else if (fam == 3) cnt += C[cm * LP + v];  // x + y = c
+                    else if (fam == 4) cnt += C[cp * LP + v];  // x - y = c
+                    else if (fam == 5) cnt += D[cm * LP + v];  // x + z = c
+                    else if (fam == 6) cnt += D[cp * LP + v];  // x - z = c
+                    else if (fam == 7) cnt += R[v + LP * cm];  // y + z = c
+                    else cnt += R[v + LP * vm];                // y - z = c
+                }
+                part[fam][chunk][c] = cnt;
+            }
+        }
+        __syncthreads();
         for (int task = tid; task < NPLANE * L; task += T) {
             const int fam = task / L, c = task - fam * L;
             int cnt = 0;
-#pragma unroll
-            for (int v = 0; v < L; ++v) {
-                const int cm = c - v < 0 ? c - v + L : c - v;    // c - v mod L
-                const int cp = c + v >= L ? c + v - L : c + v;   // c + v mod L
-                const int vm = v - c < 0 ? v - c + L : v - c;    // v - c mod L
-                switch (fam) {
-                case 0: cnt += C[c * LP + v]; break;   // x = c
-                case 1: cnt += C[v * LP + c]; break;   // y = c
-                case 2: cnt += D[v * LP + c]; break;   // z = c
-                case 3: cnt += C[cm * LP + v]; break;  // x + y = c
-                case 4: cnt += C[cp * LP + v]; break;  // x - y = c
-                case 5: cnt += D[cm * LP + v]; break;  // x + z = c
-                case 6: cnt += D[cp * LP + v]; break;  // x - z = c
-                case 7: cnt += R[v + LP * cm]; break;  // y + z = c
-                default: cnt += R[v + LP * vm]; break; // y - z = c
-                }
-            }
+            for (int g = 0; g < GC; ++g) cnt += part[fam][g][c];
             P[fam][c] = 2 * cnt - L2;
         }
         __syncthreads();

@@ -162,9 +162,18 @@ def test_batch_invariance(torch_cuda):
     assert np.array_equal(ms_all["acc"][5], ms_one["acc"][0])
 
 
-def test_checkpoint_resume(torch_cuda):
+def _resume_cases():
+    return [W.config_workload("L8_gauss", samples=[11, 12], measure_start=10),
+            W.make_workload([12, 6], [16, 5], (0.5, 1.6), [0.1, 0.3], measure_start=10, name="group resume"),
+            W.make_workload([32, 8, 10], [4, 6, 7], (0.5, 2.0), 0.4, jkind=W.J_PM1, measure_start=10,
+                            name="bits+group pm1 resume")]
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_checkpoint_resume(torch_cuda, case):
     from paper_1403_4560_amd import binding
-    work = W.config_workload("L8_gauss", samples=[11, 12], measure_start=10)
+    work = _resume_cases()[case]
+    print("case:", work.name, flush=True)
     st_full, ms_full, _ = gpu_run(work, 80)
     with binding.Ensemble(work) as a:
         a.sweep_pt(35)
@@ -176,7 +185,7 @@ def test_checkpoint_resume(torch_cuda):
         b.sweep_pt(45)
         st2 = b.read_state()
         ms2 = b.measure()
-    for s in range(2):
+    for s in range(work.n_samples):
         assert np.array_equal(st2["spins"][s], st_full["spins"][s])
         assert np.array_equal(st2["E"][s], st_full["E"][s])
         assert np.array_equal(ms2["acc"][s], ms_full["acc"][s])
