@@ -224,6 +224,18 @@ ea_status ea_synchronize(ea_ensemble *ens);
 ea_status ea_query(const ea_ensemble *ens, int32_t *n_samples, int64_t *total_slots,
                    int64_t *device_bytes);
 
+/* The engine that runs each sample's sweeps (chosen at creation from L, n_T,
+ * the coupling kind, the field, the LDS size and the tier option).
+ * engines_host [S] (caller-owned) receives one ea_engine value per sample. */
+enum {
+    EA_ENGINE_SITE = 0,   /* LDS, one site of one walker per thread step        */
+    EA_ENGINE_ROW = 1,    /* LDS, int8x4 words of one walker (Gaussian, 8, 16)  */
+    EA_ENGINE_GROUP = 2,  /* LDS, int8x4 words of one site of four walkers      */
+    EA_ENGINE_BITS = 3,   /* LDS, one bit per spin (+-1, L = 8, 16, 32)         */
+    EA_ENGINE_HBM = 4     /* HBM-resident, four launches per sweep              */
+};
+ea_status ea_query_engines(const ea_ensemble *ens, int32_t *engines_host);
+
 /* Device self-check of the acceptance shortcut used by the sweep kernels.
  * The kernels estimate a = 2^(x log2 e) with the hardware exponential and form
  * lo = a (2^32 - 2^16) - 2^-90, hi = a (2^32 + 2^17) + 512; a random word w

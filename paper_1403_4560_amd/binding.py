@@ -74,6 +74,7 @@ _SIGS = [
     ("ea_kernel_time", ctypes.c_int, [_VP, _VP, _VP]),
     ("ea_synchronize", ctypes.c_int, [_VP]),
     ("ea_query", ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    ("ea_query_engines", ctypes.c_int, [_VP, _VP]),
     ("ea_verify_exp_bracket", ctypes.c_int, [_VP, _VP]),
     ("ea_destroy", None, [_VP]),
     ("ea_last_error", ctypes.c_char_p, []),
@@ -113,6 +114,7 @@ def _p(a: np.ndarray):
 
 
 TIER_AUTO, TIER_HBM, TIER_BYTES, TIER_SITE = 0, 1, 2, 3
+ENGINE_NAMES = ["site", "row", "group", "bits", "hbm"]
 
 
 class Ensemble:
@@ -280,3 +282,9 @@ class Ensemble:
         s, t, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
         _check(load().ea_query(self._h, ctypes.byref(s), ctypes.byref(t), ctypes.byref(b)))
         return {"n_samples": s.value, "total_slots": t.value, "device_bytes": b.value}
+
+    def engines(self) -> list:
+        """Engine name per sample: site, row, group, bits or hbm."""
+        out = np.zeros(self.S, dtype=np.int32)
+        _check(load().ea_query_engines(self._h, _p(out)))
+        return [ENGINE_NAMES[int(v)] for v in out]

@@ -1270,6 +1270,17 @@ ea_status ea_query(const ea_ensemble *e, int32_t *n_samples, int64_t *total_slot
     return EA_OK;
 }
 
+ea_status ea_query_engines(const ea_ensemble *e, int32_t *engines)
+{
+    if (!e || !engines) return fail(EA_EINVAL, "null argument");
+    for (int s = 0; s < e->S; ++s) {
+        const auto &c = e->classes[e->sample_class[s]];
+        engines[s] = c.hbm ? EA_ENGINE_HBM : c.bits ? EA_ENGINE_BITS : c.group ? EA_ENGINE_GROUP
+                     : c.row ? EA_ENGINE_ROW : EA_ENGINE_SITE;
+    }
+    return EA_OK;
+}
+
 ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev)
 {
     if (!violations || !max_rel_dev) return fail(EA_EINVAL, "null argument");

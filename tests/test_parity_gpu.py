@@ -367,3 +367,25 @@ def test_row_engine_partial_waves(torch_cuda):
     work = W.make_workload([16, 16, 16, 8, 8], [1, 5, 23, 3, 17], (0.4, 1.5), [0.1, 0.2, 0.0, 0.3, 0.1],
                            measure_every=4, measure_start=2, name="row partial waves")
     check(work, 18, plan=dict(chunk=6))
+
+
+def test_engine_routing(torch_cuda):
+    """Which engine each sample runs on, by size, coupling kind, field and tier."""
+    from paper_1403_4560_amd import binding
+    gauss = W.make_workload([16, 8, 12, 6, 4, 2, 24, 16], [24, 16, 16, 16, 8, 3, 2, 64], (0.5, 2.0), 0.1,
+                            name="routing gauss")
+    with binding.Ensemble(gauss) as e:
+        # L = 4 with 8 temperatures has too few (quad, site group) items for the
+        # group engine; L = 16 with 64 temperatures does not fit LDS at all
+        assert e.engines() == ["row", "row", "group", "group", "site", "site", "hbm", "hbm"]
+    with binding.Ensemble(gauss.subset([0, 1, 2]), tier=3) as e:
+        assert e.engines() == ["site"] * 3
+    with binding.Ensemble(gauss.subset([0, 1]), tier=1) as e:
+        assert e.engines() == ["hbm"] * 2
+    pm1 = W.make_workload([32, 16, 8, 10, 32], [32, 24, 16, 56, 40], (0.5, 2.0), 0.4, jkind=W.J_PM1,
+                          name="routing pm1")
+    with binding.Ensemble(pm1) as e:
+        # 40 temperatures at L = 32 do not fit LDS at one bit per spin
+        assert e.engines() == ["bits", "bits", "bits", "group", "hbm"]
+    with binding.Ensemble(pm1.subset([0, 1, 2]), tier=2) as e:
+        assert e.engines() == ["hbm", "group", "group"]
