@@ -415,8 +415,10 @@ __global__ void __launch_bounds__(1024) site_sweep_kernel(SweepArgs A)
     }
 }
 
+// L = 8 chains are small (two waves for 16 walkers), so their workgroups are
+// held to 128 VGPRs to keep four waves per SIMD resident.
 template <int L, int VAR>
-__global__ void __launch_bounds__(ROW_MAX_THREADS) row_sweep_kernel(SweepArgs A)
+__global__ void __launch_bounds__(ROW_MAX_THREADS, L == 8 ? 4 : 1) row_sweep_kernel(SweepArgs A)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
