@@ -13,7 +13,9 @@ measurements of every slot.  The metric is spin-flip attempts per ns
 (one attempt = one Metropolis trial at one site of one walker).
 
 Prints one JSON line (rank 0).  Besides the headline value it reports the
-unbatched form (the same kernels, one launch per sample, on a 64-sample subset),
+unbatched form (the same kernels, one launch per sample, on a 64-sample subset,
+and, for L divisible by 8, the HBM-resident kernels that spread one sample's
+walkers over many workgroups, one sample per launch, on 16 samples),
 the roofline of the dominant kernel from HIP events recorded around each of
 its launches, and the CPU oracle on a bounded sample.
 """
@@ -210,6 +212,23 @@ def main():
         unbatched = {"value": ub_value, "unit": "attempts/ns", "samples": sub.n_samples,
                      "sweeps": SWEEPS_PER_STEP * args.unbatched_steps,
                      "batched_over_unbatched": value / ub_value}
+        if all(int(L) % 8 == 0 for L in work.L):
+            # the stronger one-sample-per-launch form: the HBM-resident kernels
+            # spread one sample's walkers over many workgroups per launch
+            sub2 = work.subset(range(min(16, work.n_samples)))
+            ub2 = binding.Ensemble(sub2, stream=stream.cuda_stream, tier=1)
+            ub2.sweep_pt_unbatched(10)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            ub2.sweep_pt_unbatched(SWEEPS_PER_STEP)
+            torch.cuda.synchronize()
+            dt2 = time.perf_counter() - t2
+            ub2.close()
+            v2 = sub2.attempts_per_sweep() * SWEEPS_PER_STEP / (dt2 * 1e9)
+            progress("unbatched, HBM-resident spread: %.1f attempts/ns" % v2)
+            unbatched["spread_form"] = {"value": v2, "samples": sub2.n_samples, "sweeps": SWEEPS_PER_STEP,
+                                        "batched_over_spread": value / v2,
+                                        "kernels": "HBM-resident half-sweep, exchange, snapshot per sweep"}
 
     cpu = None
     if not args.no_cpu:

@@ -191,9 +191,13 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     for (int h = tid; h < HALF; h += T) NB[h] = nbr_entry<L>(h);
     if constexpr (JK == 0) {
         // couplings as exact int32 multiples of 2^-18
-        const float *src = (const float *)A.J + d.J_off;
-        int *dst = (int *)Jl;
-        for (int i = tid; i < 3 * N; i += T) dst[i] = (int)(src[i] * 262144.0f);
+        const float4 *src = (const float4 *)((const float *)A.J + d.J_off);  // J_off is a multiple of 4
+        int4 *dst = (int4 *)Jl;
+        for (int i = tid; i < 3 * N / 4; i += T) {
+            const float4 v = src[i];
+            dst[i] = make_int4((int)(v.x * 262144.0f), (int)(v.y * 262144.0f), (int)(v.z * 262144.0f),
+                               (int)(v.w * 262144.0f));
+        }
     } else {
         block_copy(Jl, (const int8_t *)A.J + d.J_off, (size_t)3 * N);
         for (int i = tid; i < nT * 14; i += T) lut[i] = A.lut[(size_t)d.slot_off * 14 + i];

@@ -8,14 +8,24 @@
 
 namespace ea {
 
-// Block-cooperative byte copy, 16 bytes at a time when both ends allow it.
-__device__ __forceinline__ void block_copy(void *dst, const void *src, size_t bytes)
+// Block-cooperative byte copy, 16 bytes at a time when both ends allow it;
+// four copies in flight per thread.
+__device__ __forceinline__ void block_copy(void *__restrict__ dst, const void *__restrict__ src, size_t bytes)
 {
     const int T = blockDim.x, tid = threadIdx.x;
     if ((((uintptr_t)dst | (uintptr_t)src | bytes) & 15) == 0) {
-        int4 *d = (int4 *)dst;
-        const int4 *s = (const int4 *)src;
-        for (size_t i = tid; i < bytes / 16; i += T) d[i] = s[i];
+        int4 *__restrict__ d = (int4 *)dst;
+        const int4 *__restrict__ s = (const int4 *)src;
+        const size_t n = bytes / 16;
+        size_t i = tid;
+        for (; i + 3 * (size_t)T < n; i += 4 * (size_t)T) {
+            const int4 a = s[i], b = s[i + T], c = s[i + 2 * T], e = s[i + 3 * T];
+            d[i] = a;
+            d[i + T] = b;
+            d[i + 2 * T] = c;
+            d[i + 3 * T] = e;
+        }
+        for (; i < n; i += T) d[i] = s[i];
     } else {
         int8_t *d = (int8_t *)dst;
         const int8_t *s = (const int8_t *)src;

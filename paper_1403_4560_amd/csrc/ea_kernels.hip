@@ -293,9 +293,13 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
     block_copy(I.S, A.spins + sbase, (size_t)nT * N);
     if constexpr (ROW) {
         // couplings as exact int32 multiples of 2^-18
-        const float *src = (const float *)A.J + d.J_off;
-        int *dst = (int *)I.J;
-        for (int i = tid; i < 3 * N; i += T) dst[i] = (int)(src[i] * 262144.0f);
+        const float4 *src = (const float4 *)((const float *)A.J + d.J_off);  // J_off is a multiple of 4
+        int4 *dst = (int4 *)I.J;
+        for (int i = tid; i < 3 * N / 4; i += T) {
+            const float4 v = src[i];
+            dst[i] = make_int4((int)(v.x * 262144.0f), (int)(v.y * 262144.0f), (int)(v.z * 262144.0f),
+                               (int)(v.w * 262144.0f));
+        }
     } else {
         block_copy(I.J, (const char *)A.J + (size_t)d.J_off * (JK == 0 ? 4 : 1),
                    (size_t)3 * N * (JK == 0 ? 4 : 1));
