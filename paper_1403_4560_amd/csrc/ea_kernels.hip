@@ -13,13 +13,18 @@
 // (eq. 2), so they are independent work items; the measurement kernel
 // combines their snapshots after the chunk.
 //
-// Two half-sweep engines share that frame:
+// Two half-sweep engines share that frame here:
 //  * row engine (L = 8, 16; Gaussian couplings): a thread owns one walker and
 //    one (x-word, y) column and walks z; it works on 4 sites at once (one int8x4
 //    word = one Philox call), keeps couplings as integer 2^-18 units and the
 //    walker's energy/flip tallies in registers for the whole sweep;
-//  * site engine (any even L <= 16, either coupling kind): a thread takes a
-//    4-site group of any walker and updates its sites one by one.
+//  * site engine (any even L <= 16, either coupling kind; chains too small for
+//    the group engine): a thread takes a 4-site group of any walker and updates
+//    its sites one by one.
+// The group engine (ea_group.hip: one word = one site of four walkers) and the
+// one-bit engine (ea_bits.hip: +-1 couplings) use the same frame with their
+// own LDS layouts.  This file also holds the HBM-resident tier, the overlap
+// measurement, the finalize and the setup and check kernels.
 #include "ea_device.hpp"
 #include "ea_item.hpp"
 #include "ea_types.hpp"
