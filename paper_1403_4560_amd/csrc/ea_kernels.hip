@@ -737,6 +737,7 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
     __shared__ int part[NPLANE][GC][L];
     __shared__ double accs[NACC];
     __shared__ double re_f[NPLANE], im_f[NPLANE];
+    __shared__ double cst[L], snt[L];  // cos and sin of 2 pi c / L
     const int gs = A.slots[blockIdx.x];
     const int s = A.slot_sample[gs];
     const SampleDev d = A.samples[s];
@@ -752,10 +753,21 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
     }
     if (nf <= 0) return;
     for (int i = tid; i < NACC; i += T) accs[i] = A.acc[(size_t)gs * NACC + i];
+    for (int c = tid; c < L; c += T) {
+        cst[c] = A.costab[(size_t)L * MAX_L + c];
+        snt[c] = A.sintab[(size_t)L * MAX_L + c];
+    }
     constexpr double Nd = (double)(L2 * L);
     for (int64_t f = 0; f < nf; ++f) {
         const uint32_t *ra = A.frames + f * A.frame_words + d.frame_off + (size_t)t * L2;
         const uint32_t *rb = ra + (size_t)d.n_T * L2;
+        // the frame's two energies, loaded early (used after the plane sums)
+        double Ea = 0.0, Eb = 0.0;
+        if (tid == NPLANE) {
+            const double *E = A.frameE + f * 2 * A.total_slots + 2 * (size_t)d.slot_off;
+            Ea = E[t];
+            Eb = E[d.n_T + t];
+        }
         for (int i = tid; i < L2; i += T) {
             const uint32_t e = ~(ra[i] ^ rb[i]) & mask;
             const int y = i % L, z = i / L;
@@ -799,11 +811,10 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
         }
         __syncthreads();
         if (tid < NPLANE) {
-            const double *ct = A.costab + (size_t)L * MAX_L, *st = A.sintab + (size_t)L * MAX_L;
             double re = 0.0, im = 0.0;
             for (int c = 0; c < L; ++c) {
-                re += (double)P[tid][c] * ct[c];
-                im += (double)P[tid][c] * st[c];
+                re += (double)P[tid][c] * cst[c];
+                im += (double)P[tid][c] * snt[c];
             }
             re_f[tid] = re / Nd;
             im_f[tid] = im / Nd;
@@ -823,8 +834,6 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
             accs[2] += q0 * q0;
             accs[3] += (q0 * q0) * q0;
             accs[4] += (q0 * q0) * (q0 * q0);
-            const double *E = A.frameE + f * 2 * A.total_slots + 2 * (size_t)d.slot_off;
-            const double Ea = E[t], Eb = E[d.n_T + t];
             accs[32] += Ea;
             accs[33] += Ea * Ea;
             accs[34] += Eb;
