@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "spin-flip attempts/ns at L=16 batched vs unbatched; bit-exact spins"
 SWEEPS_PER_STEP = 100
 KERNEL = {"L16_gauss": "row_sweep_kernel<16, 0>", "L8_gauss": "row_sweep_kernel<8, 0>",
-          "L4_gauss": "group_sweep_kernel<4, 0, 0>", "mixed_L6_12": "group/row sweep kernels (4 sizes)",
+          "L4_gauss": "site_sweep_kernel<4, 0, 0>", "mixed_L6_12": "group/row sweep kernels (4 sizes)",
           "L32_pm1": "bits_sweep_kernel<32, 0>"}
 WORKLOAD_TEXT = {
     "L16_gauss": "L16_gauss: L=16, 2048 samples, 24 temperatures geometric in T=[0.4,1.5], 2 replicas, "

@@ -238,13 +238,14 @@ ea_status ea_query_engines(const ea_ensemble *ens, int32_t *engines_host);
 
 /* Device self-check of the acceptance shortcut used by the sweep kernels.
  * The kernels estimate a = 2^(x log2 e) with the hardware exponential and form
- * lo = a (2^32 - 2^16) - 2^-90, hi = a (2^32 + 2^17) + 512; a random word w
- * with fl32(w) < lo is accepted and one with fl32(w) >= hi rejected without
- * evaluating the in-house exp_ea32, any other word by the exact test.  This
- * call checks, for every binary32 x in [-86, 0] (1.1e9 values), that both
- * shortcuts decide as the exact test U 2^-24 < exp_ea32(x), U = w >> 8, would
- * for every w, and for every binary32 x below -86 (where exp_ea32 is 0) that
- * lo <= 0.  *violations must be 0; *max_rel_dev is the largest
+ * the gap g = fl32(fl32(w) - a 2^32) for the random word w; g < -8192 accepts
+ * and g > 8192 rejects without evaluating the in-house exp_ea32, any other
+ * word takes the exact test (x >= 0 or U 2^-24 < exp_ea32(x), U = w >> 8).
+ * This call checks, over every non-NaN binary32 x (4.3e9 values), the bounds
+ * on a that make both shortcuts decide as the exact test would for every w:
+ * for x <= 0 that a 2^32 lies within 8192 - 384 below and 8192 - 128 above
+ * exp_ea32(x) 2^32 (exp_ea32 = 0 below -86), for x > 0 that a 2^32 >=
+ * 2^32 - 8192 + 384.  *violations must be 0; *max_rel_dev is the largest
  * |a/exp_ea32(x) - 1| seen on [-86, 0].  Synchronizing; uses the current
  * device. */
 ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev);

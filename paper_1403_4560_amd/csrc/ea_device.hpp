@@ -113,22 +113,30 @@ __device__ __forceinline__ double exp_ea64(double x)
     return x < -700.0 ? 0.0 : v;
 }
 
-// Acceptance bracket.  For x <= 0 the hardware estimate a = 2^(x log2 e) lies
-// within a relative 2^-17 of exp_ea32(x) (checked exhaustively on the device by
-// ea_verify_exp_bracket).  With W = fl32(w) for the 32-bit random word w and
-// U = w >> 8 the 24-bit uniform numerator, the bounds
-//   lo = a (2^32 - 2^16) - 2^-90,   hi = a (2^32 + 2^17) + 512
-// satisfy: W < lo implies U < exp_ea32(x) 2^24 (accept), and W >= hi implies
-// U >= exp_ea32(x) 2^24 (reject), for every x in [-86, 0]; the verification
-// checks exactly these two implications.  Below -86, where exp_ea32 is 0, a is
-// under 2^-124 and lo is negative, so no word is accepted by the bracket; the
-// verification checks that too.  Between the bounds the exact test decides.
-__device__ __forceinline__ void accept_bracket(float x, float &lo, float &hi)
+// Acceptance gap.  The engines form the exponent y = fl32(c' f) with the
+// per-slot constant c' = -fl32(2 beta32 log2 e) signed like c = -2 beta32 s_i,
+// so y = x log2(e) (1 + e), |e| < 3.01 2^-24, for x = fl32(c f) =
+// -fl32(beta32 dE) (three roundings: c', y, x), and the hardware estimate
+// a = 2^y of exp_ea32(x).  With W = fl32(w) for the 32-bit random word w (so
+// |W - w| <= 128), U = w >> 8 the 24-bit uniform numerator, A = a 2^32,
+// T = exp_ea32(x) 2^32 and the gap g = fl32(W - A) (one fused rounding):
+//   g < -M  =>  W - A < -M  =>  U <= w/256 < (A - M + 128)/256,
+//   g >  M  =>  W - A >  M  =>  U >  w/256 - 1 > (A + M - 384)/256,
+// so T - (M - 384) <= A <= T + (M - 128) makes g < -M a correct accept and
+// g > M a correct reject.  ea_verify_exp_bracket checks, for every binary32 x,
+// that pair of inequalities (T = 0 below -86; for x > 0, where the exact test
+// accepts, only A >= 2^32 - M + 384, so that g > M cannot happen) at both ends
+// of the range of a over every y within a relative 2^-21 of x log2(e), using
+// that the hardware exponential is monotone (checked on every binary32 input
+// by the same call).  Inside [-M, M] the exact test decides.
+constexpr float ACCEPT_MARGIN = 8192.0f;  // M
+
+// c' of a slot: -fl32(2 beta32 log2 e), one rounding (2 beta32 is exact).
+__device__ __forceinline__ float neg2beta_log2e(float b32) { return (-2.0f * b32) * __uint_as_float(0x3FB8AA3Bu); }
+
+__device__ __forceinline__ float accept_gap(float y, float W)
 {
-    const float LOG2E = __uint_as_float(0x3FB8AA3Bu);
-    const float a = __builtin_amdgcn_exp2f(x * LOG2E);
-    lo = __builtin_fmaf(a, 4294901760.0f, -0x1p-90f);  // 2^32 - 2^16
-    hi = __builtin_fmaf(a, 4295098368.0f, 512.0f);     // 2^32 + 2^17, plus 2 units of U
+    return __builtin_fmaf(__builtin_amdgcn_exp2f(y), -0x1p32f, W);
 }
 
 // 24-bit and 53-bit uniforms in [0, 1) from Philox output words.

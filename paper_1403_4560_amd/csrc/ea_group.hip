@@ -63,10 +63,11 @@ __device__ __forceinline__ uint4 nbr_entry(int h)
 }
 
 struct GroupLane {
-    float m2b[4];           // -2 beta32 of each walker's slot
+    float cl[4];            // neg2beta_log2e of each walker's slot
     uint32_t c2[4];         // Philox counter word 2 of each walker
     uint32_t thr[4];        // +-1: offset of each walker's threshold table in lut
     uint32_t valid;         // 0xFF in the bytes of real walkers
+    float h32;              // the sample's field, held in a vector register
 };
 
 struct GroupTally {
@@ -79,8 +80,8 @@ struct GroupTally {
 // Metropolis update of work item (quad q, sites 4 g4 .. 4 g4 + 3) of parity P.
 template <int L, int JK, int P>
 __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &d, uint32_t *SG, const void *Jl,
-                                           const uint32_t *lut, const uint4 *NB, int NQ, int q, int g4, uint32_t c1,
-                                           const GroupLane &ln, GroupTally &ty)
+                                           const uint32_t *lut, const float *b32, const uint4 *NB, int NQ, int q,
+                                           int g4, uint32_t c1, const GroupLane &ln, GroupTally &ty)
 {
     constexpr int HALF = L * L * L / 2, PS = HALF + 1;
     uint32_t *Sp = SG + (P * NQ + q) * PS;
@@ -113,8 +114,9 @@ __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &
             const int Ja[4] = {jx, jx, jx, jx}, Js[4] = {jxm, jxm, jxm, jxm};
             const int Jy[4] = {jy, jy, jy, jy}, Jyn[4] = {jym, jym, jym, jym};
             const int Jz[4] = {jz, jz, jz, jz}, Jzn[4] = {jzm, jzm, jzm, jzm};
-            fm = update_word_gauss(Sv, X[0], X[1], X[2], X[3], X[4], X[5], Ja, Js, Jy, Jyn, Jz, Jzn, rk, ln.m2b,
-                                   d.h32, Sus) &
+            // the exact path reads 2 beta32 of walker i's slot, t = bits 1 .. 27 of its counter word
+            fm = update_word_gauss(Sv, X[0], X[1], X[2], X[3], X[4], X[5], Ja, Js, Jy, Jyn, Jz, Jzn, rk, ln.cl,
+                                   [&](int i) { return 2.0f * b32[(ln.c2[i] >> 1) & 0x7FFFFFFu]; }, ln.h32, Sus) &
                  ln.valid;
         } else {
             // bond-spin product bytes J s_j: 0x01 (+1) or 0xFF (-1); c counts the -1
@@ -236,22 +238,26 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         for (int i = 0; i < 4; ++i) {
             const int w = 4 * q + i;
             ts[i] = w < nT ? I.sow[w] : 0;
-            ln.m2b[i] = -2.0f * I.b32[ts[i]];
+            ln.cl[i] = neg2beta_log2e(I.b32[ts[i]]);
             ln.c2[i] = (PURPOSE_METROPOLIS << 28) | ((uint32_t)ts[i] << 1) | (uint32_t)r;
             ln.thr[i] = 14 * ts[i];
         }
         ln.valid = valid;
+        ln.h32 = d.h32;
+        asm volatile("" : "+v"(ln.h32));
         GroupTally ty;
         if (on) {
             const uint32_t c1 = (uint32_t)(2 * n);
 #pragma unroll 1
-            for (int g4 = gs; g4 < G4; g4 += TPQ) group_item<L, JK, 0>(A, d, SG, Jl, lut, NB, NQ, q, g4, c1, ln, ty);
+            for (int g4 = gs; g4 < G4; g4 += TPQ)
+                group_item<L, JK, 0>(A, d, SG, Jl, lut, I.b32, NB, NQ, q, g4, c1, ln, ty);
         }
         __syncthreads();
         if (on) {
             const uint32_t c1 = (uint32_t)(2 * n + 1);
 #pragma unroll 1
-            for (int g4 = gs; g4 < G4; g4 += TPQ) group_item<L, JK, 1>(A, d, SG, Jl, lut, NB, NQ, q, g4, c1, ln, ty);
+            for (int g4 = gs; g4 < G4; g4 += TPQ)
+                group_item<L, JK, 1>(A, d, SG, Jl, lut, I.b32, NB, NQ, q, g4, c1, ln, ty);
             for (int i = 0; i < 4; ++i) {
                 const int w = 4 * q + i;
                 if (w >= nT) break;
@@ -320,7 +326,7 @@ __global__ void __launch_bounds__(GROUP_MAX_THREADS, 4) group_sweep_kernel(Sweep
     extern __shared__ __attribute__((aligned(16))) char smem[];
     for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
         const int code = A.items[item];
-        run_group_item<L, JK>(A, A.samples[code >> 1], code & 1, smem);
+        run_group_item<L, JK>(A, sample_of_item(A.samples, code >> 1), code & 1, smem);
     }
 }
 

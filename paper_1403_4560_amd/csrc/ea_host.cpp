@@ -1284,9 +1284,9 @@ ea_status ea_query_engines(const ea_ensemble *e, int32_t *engines)
 ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev)
 {
     if (!violations || !max_rel_dev) return fail(EA_EINVAL, "null argument");
-    const uint32_t first = 0x80000000u;                 // -0.0
-    const uint32_t last = 0xFF800000u;                  // -inf
-    const uint32_t count = last - first + 1;
+    // every non-NaN binary32: +0 .. +inf, then -0 .. -inf
+    const uint32_t firsts[2] = {0x00000000u, 0x80000000u};
+    const uint32_t count = 0x7F800001u;
     unsigned long long *dv = nullptr;
     unsigned int *dm = nullptr;
     if (hipMalloc(&dv, sizeof *dv) != hipSuccess) return fail(EA_ENOMEM, "hipMalloc failed");
@@ -1297,8 +1297,11 @@ ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev)
     hipError_t st = hipMemset(dv, 0, sizeof *dv);
     if (st == hipSuccess) st = hipMemset(dm, 0, sizeof *dm);
     if (st == hipSuccess) {
-        hipLaunchKernelGGL(exp_bracket_kernel, dim3((count + 255) / 256), dim3(256), 0, nullptr, first, count, dv, dm);
-        st = hipGetLastError();
+        for (int k = 0; k < 2 && st == hipSuccess; ++k) {
+            hipLaunchKernelGGL(exp_bracket_kernel, dim3((count + 255) / 256), dim3(256), 0, nullptr, firsts[k],
+                               count, dv, dm);
+            st = hipGetLastError();
+        }
     }
     unsigned long long v = 0;
     unsigned int m = 0;

@@ -83,6 +83,22 @@ struct ItemLds {
     double *b64;
 };
 
+// The descriptor of a workgroup's sample, read into scalar registers: the
+// item code is the same for every lane, and descriptors are read-only during a
+// launch, so the read may go through the scalar cache.
+__device__ __forceinline__ SampleDev sample_of_item(const SampleDev *samples, int idx)
+{
+    typedef const __attribute__((address_space(4))) uint32_t *ConstWords;
+    static_assert(sizeof(SampleDev) % 4 == 0, "descriptor is read in 32-bit words");
+    const ConstWords src = (ConstWords)(samples + __builtin_amdgcn_readfirstlane(idx));
+    uint32_t w[sizeof(SampleDev) / 4];
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(SampleDev) / 4); ++k) w[k] = src[k];
+    SampleDev d;
+    __builtin_memcpy(&d, w, sizeof d);
+    return d;
+}
+
 __device__ __forceinline__ ItemLds item_lds(char *smem, int L, int nT, int jkind)
 {
     const LdsOff o = lds_offsets(L, nT, jkind);

@@ -196,7 +196,7 @@ struct RowMap {
 template <int L, int P, int EPS>
 __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d, uint8_t *Sw, const int *J,
                                          int o_y0, int o_yp, int o_ym, int o_x, int e_prev, int z, int zp,
-                                         int zm, uint32_t c1, uint32_t c2, float m2b, int &accE, int &nd,
+                                         int zm, uint32_t c1, uint32_t c2, float cl, float h32, int &accE, int &nd,
                                          int &bf, int &bd)
 {
     constexpr int HALF = L * L * L / 2, HL = L / 2, PLANE = L * HL;
@@ -231,9 +231,11 @@ __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d,
     const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
     const uint32_t g = (uint32_t)(o_y0 / 4 + z * (PLANE / 4));
     const u32x4 rw = philox4x32_10(g, c1, c2, d.sample_id, A.key0, A.key1);
-    const float m2bv[4] = {m2b, m2b, m2b, m2b};
+    const float clv[4] = {cl, cl, cl, cl};
     int Sus[4];
-    const uint32_t fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2bv, d.h32, Sus);
+    const uint32_t fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, clv,
+                                          [&](int) { return 2.0f * A.beta32[d.slot_off + ((c2 >> 1) & 0x7FFFFFFu)]; },
+                                          h32, Sus);
     if constexpr (P == 1) tally_final(Sv, fm, Sus, accE, nd);
     *(uint32_t *)(Sw + P * HALF + o_y0 + zo) = Sv ^ fm;
     bf += __builtin_popcount(fm);
@@ -256,14 +258,17 @@ __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleD
     const int *J = (const int *)I.J;
     const uint32_t c1 = (uint32_t)(2 * n + P);
     const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
-    const float m2b = -2.0f * I.b32[t];
+    const float cl = neg2beta_log2e(I.b32[t]);
+    // the field in a vector register: every site's fused add takes it there
+    float h32 = d.h32;
+    asm volatile("" : "+v"(h32));
 #pragma unroll 1
     for (int z = 0; z < L; z += 2) {
         const int zm = z == 0 ? L - 1 : z - 1, zpp = z + 2 == L ? 0 : z + 2;
-        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z, z + 1, zm, c1, c2, m2b, accE, nd, bf,
-                           bd);
-        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, zpp, z, c1, c2, m2b, accE, nd,
-                               bf, bd);
+        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z, z + 1, zm, c1, c2, cl, h32, accE, nd,
+                           bf, bd);
+        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, zpp, z, c1, c2, cl, h32, accE,
+                               nd, bf, bd);
     }
 }
 
@@ -432,7 +437,7 @@ __global__ void __launch_bounds__(ROW_MAX_THREADS, L == 8 ? 4 : 1) row_sweep_ker
     extern __shared__ __attribute__((aligned(16))) char smem[];
     for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
         const int code = A.items[item];
-        run_item<L, 0, true>(A, A.samples[code >> 1], code & 1, smem);
+        run_item<L, 0, true>(A, sample_of_item(A.samples, code >> 1), code & 1, smem);
     }
 }
 
@@ -518,7 +523,8 @@ __global__ void __launch_bounds__(256) hbm_half_kernel(SweepArgs A)
     const uint8_t *oth = Sw + (1 - p) * HALF;
     const uint32_t c1 = (uint32_t)(2 * n + p);
     const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
-    const float m2b = -2.0f * A.beta32[d.slot_off + t];
+    const float b32 = A.beta32[d.slot_off + t];
+    const float cl = neg2beta_log2e(b32);
     int accE = 0, bf = 0, bd = 0;
     for (int j = 0; j < (TILE + 255) / 256; ++j) {
         const int g = tile * TILE + j * 256 + tid;
@@ -555,9 +561,10 @@ __global__ void __launch_bounds__(256) hbm_half_kernel(SweepArgs A)
             const int Js[4] = {eps ? Jpx.x : Ep, eps ? Jpx.y : V.x, eps ? Jpx.z : V.y, eps ? Jpx.w : V.z};
             const int Jy[4] = {Jpy.x, Jpy.y, Jpy.z, Jpy.w}, Jyn[4] = {Jym.x, Jym.y, Jym.z, Jym.w};
             const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
-            const float m2bv[4] = {m2b, m2b, m2b, m2b};
+            const float clv[4] = {cl, cl, cl, cl};
             int Sus[4];
-            fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, m2bv, d.h32, Sus);
+            fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, clv,
+                                   [=](int) { return 2.0f * b32; }, d.h32, Sus);
             accE += tally_delta(Sv, fm, Sus);
         } else {
             const uint8_t *J8 = (const uint8_t *)A.J + d.J_off;
@@ -857,34 +864,59 @@ EA_MEAS(24)
 EA_MEAS(32)
 #undef EA_MEAS
 
-// Exhaustive check of the acceptance bracket used by the row and HBM engines,
-// for every binary32 x in [-86, 0], in binary64:
-//   lo (1 + 2^-24) <= 256 E24        (W < lo  =>  U < E24, E24 = exp_ea32(x) 2^24)
-//   hi (1 - 2^-24) / 256 - 1 >= E24  (W >= hi =>  U >= E24)
-// where W = fl32(w) is within a relative 2^-24 of w and U = w >> 8 >= w/256 - 1;
-// and for every binary32 x below -86 (down to -inf), where exp_ea32 is 0,
-// lo <= 0, so that no W >= 0 is accepted by the bracket alone.
-// Also records the largest |a / exp_ea32(x) - 1| of the hardware estimate.
+// Neighbouring binary32 values (by bit pattern; -0 and +0 step to the
+// smallest subnormals, infinities stay).
+__device__ __forceinline__ float float_up(float v)
+{
+    if (v == __builtin_inff()) return v;
+    if (v == 0.0f) return __uint_as_float(1u);
+    const uint32_t b = __float_as_uint(v);
+    return __uint_as_float(v > 0.0f ? b + 1u : b - 1u);
+}
+__device__ __forceinline__ float float_down(float v) { return -float_up(-v); }
+
+// Exhaustive check of the acceptance gap used by the row, group and HBM
+// engines, in binary64, with M = ACCEPT_MARGIN.  One thread per binary32 bit
+// pattern v (NaNs excluded by the launch):
+// (1) the hardware exponential is monotone: 2^v <= 2^(next binary32 above v);
+// (2) for x = v: every exponent y the engines can form for x lies within a
+//     relative 2^-21 (eight times the rounding bound) of z = x log2(e), plus
+//     2^-140 for subnormal rounding; with yl, yh the binary32 values just
+//     outside that interval and A = 2^y 2^32 at both ends (exact here),
+//     T = exp_ea32(x) 2^32 (0 below -86):
+//       x <= 0:  T - (M - 384) <= A(yl)  and  A(yh) <= T + (M - 128)
+//       x > 0:   A(yl) >= 2^32 - M + 384   (dE < 0: the exact test accepts)
+// Also records the largest |A / T - 1| at the two ends over [-86, 0].
 __global__ void exp_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned long long *violations,
                                    unsigned int *max_dev_bits)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const float x = __uint_as_float(first_bits + i);
-    float lo, hi;
-    accept_bracket(x, lo, hi);
-    if (!(x >= -86.0f)) {
-        // exp_ea32 is 0 here: no word may fall below the bracket
-        if (!(lo <= 0.0f)) atomicAdd(violations, 1ull);
-        return;
+    const float v = __uint_as_float(first_bits + i);
+    bool ok = true;
+    if (v != __builtin_inff() && !(__builtin_amdgcn_exp2f(v) <= __builtin_amdgcn_exp2f(float_up(v)))) ok = false;
+
+    const double TWO32 = 4294967296.0, M = ACCEPT_MARGIN;
+    const double z = (double)v * (double)__uint_as_float(0x3FB8AA3Bu);  // exact: 24 x 24 bits
+    const double B = 0x1p-21, D = 0x1p-140;
+    const double zl = (z <= 0.0 ? z * (1.0 + B) : z * (1.0 - B)) - D;
+    const double zh = (z <= 0.0 ? z * (1.0 - B) : z * (1.0 + B)) + D;
+    float yl = (float)zl, yh = (float)zh;
+    if ((double)yl > zl) yl = float_down(yl);
+    if ((double)yh < zh) yh = float_up(yh);
+    const double Al = (double)__builtin_amdgcn_exp2f(yl) * TWO32;
+    const double Ah = (double)__builtin_amdgcn_exp2f(yh) * TWO32;
+    if (v > 0.0f) {
+        ok = ok && Al >= TWO32 - M + 384.0;
+    } else {
+        const double T = v >= -86.0f ? (double)exp_ea32(v) * TWO32 : 0.0;
+        ok = ok && Al >= T - (M - 384.0) && Ah <= T + (M - 128.0);
+        if (v >= -86.0f) {
+            const float dev = (float)(fmax(fabs(Al - T), fabs(Ah - T)) / T);
+            atomicMax(max_dev_bits, __float_as_uint(dev));
+        }
     }
-    const double E24 = (double)exp_ea32(x) * 16777216.0;
-    const bool okA = (double)lo * (1.0 + 0x1p-24) <= 256.0 * E24;
-    const bool okB = (double)hi * (1.0 - 0x1p-24) / 256.0 - 1.0 >= E24;
-    if (!okA || !okB) atomicAdd(violations, 1ull);
-    const float a = __builtin_amdgcn_exp2f(x * __uint_as_float(0x3FB8AA3Bu));
-    const float dev = (float)(fabs((double)a * 16777216.0 - E24) / E24);
-    atomicMax(max_dev_bits, __float_as_uint(dev));
+    if (!ok) atomicAdd(violations, 1ull);
 }
 
 __global__ void advance_kernel(int64_t *state, int64_t k)
