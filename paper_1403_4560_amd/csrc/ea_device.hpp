@@ -113,9 +113,9 @@ __device__ __forceinline__ double exp_ea64(double x)
     return x < -700.0 ? 0.0 : v;
 }
 
-// Acceptance gap.  The engines form the exponent y = fl32(c' f) with the
-// per-slot constant c' = -fl32(2 beta32 log2 e) signed like c = -2 beta32 s_i,
-// so y = x log2(e) (1 + e), |e| < 3.01 2^-24, for x = fl32(c f) =
+// Acceptance gap.  The engines form the exponent y = fl32(c' g) with g = -s_i f
+// (exact) and the per-slot constant c' = fl32(2 beta32 log2 e), so
+// y = x log2(e) (1 + e), |e| < 3.01 2^-24, for x = fl32(2 beta32 g) =
 // -fl32(beta32 dE) (three roundings: c', y, x), and the hardware estimate
 // a = 2^y of exp_ea32(x).  With W = fl32(w) for the 32-bit random word w (so
 // |W - w| <= 128), U = w >> 8 the 24-bit uniform numerator, A = a 2^32,
@@ -131,8 +131,8 @@ __device__ __forceinline__ double exp_ea64(double x)
 // by the same call).  Inside [-M, M] the exact test decides.
 constexpr float ACCEPT_MARGIN = 8192.0f;  // M
 
-// c' of a slot: -fl32(2 beta32 log2 e), one rounding (2 beta32 is exact).
-__device__ __forceinline__ float neg2beta_log2e(float b32) { return (-2.0f * b32) * __uint_as_float(0x3FB8AA3Bu); }
+// c' of a slot: fl32(2 beta32 log2 e), one rounding (2 beta32 is exact).
+__device__ __forceinline__ float two_beta_log2e(float b32) { return (2.0f * b32) * __uint_as_float(0x3FB8AA3Bu); }
 
 __device__ __forceinline__ float accept_gap(float y, float W)
 {

@@ -63,7 +63,7 @@ __device__ __forceinline__ uint4 nbr_entry(int h)
 }
 
 struct GroupLane {
-    float cl[4];            // neg2beta_log2e of each walker's slot
+    float cl[4];            // two_beta_log2e of each walker's slot
     uint32_t c2[4];         // Philox counter word 2 of each walker
     uint32_t thr[4];        // +-1: offset of each walker's threshold table in lut
     uint32_t valid;         // 0xFF in the bytes of real walkers
@@ -238,7 +238,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         for (int i = 0; i < 4; ++i) {
             const int w = 4 * q + i;
             ts[i] = w < nT ? I.sow[w] : 0;
-            ln.cl[i] = neg2beta_log2e(I.b32[ts[i]]);
+            ln.cl[i] = two_beta_log2e(I.b32[ts[i]]);
             ln.c2[i] = (PURPOSE_METROPOLIS << 28) | ((uint32_t)ts[i] << 1) | (uint32_t)r;
             ln.thr[i] = 14 * ts[i];
         }

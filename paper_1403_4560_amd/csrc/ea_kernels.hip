@@ -258,7 +258,7 @@ __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleD
     const int *J = (const int *)I.J;
     const uint32_t c1 = (uint32_t)(2 * n + P);
     const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
-    const float cl = neg2beta_log2e(I.b32[t]);
+    const float cl = two_beta_log2e(I.b32[t]);
     // the field in a vector register: every site's fused add takes it there
     float h32 = d.h32;
     asm volatile("" : "+v"(h32));
@@ -524,7 +524,7 @@ __global__ void __launch_bounds__(256) hbm_half_kernel(SweepArgs A)
     const uint32_t c1 = (uint32_t)(2 * n + p);
     const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
     const float b32 = A.beta32[d.slot_off + t];
-    const float cl = neg2beta_log2e(b32);
+    const float cl = two_beta_log2e(b32);
     int accE = 0, bf = 0, bd = 0;
     for (int j = 0; j < (TILE + 255) / 256; ++j) {
         const int g = tile * TILE + j * 256 + tid;

@@ -7,21 +7,46 @@
 
 namespace ea {
 
+// f with its sign flipped iff byte i of m is 0x80: one SDWA xor of that byte
+// into the sign byte of f (the other bytes of f are kept).
+__device__ __forceinline__ float flip_by_byte(float f, uint32_t m, int i)
+{
+    switch (i) {
+    case 0:
+        asm("v_xor_b32_sdwa %0, %1, %0 dst_sel:BYTE_3 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_0 src1_sel:BYTE_3"
+            : "+v"(f) : "v"(m));
+        break;
+    case 1:
+        asm("v_xor_b32_sdwa %0, %1, %0 dst_sel:BYTE_3 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_1 src1_sel:BYTE_3"
+            : "+v"(f) : "v"(m));
+        break;
+    case 2:
+        asm("v_xor_b32_sdwa %0, %1, %0 dst_sel:BYTE_3 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_2 src1_sel:BYTE_3"
+            : "+v"(f) : "v"(m));
+        break;
+    default:
+        asm("v_xor_b32_sdwa %0, %1, %0 dst_sel:BYTE_3 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_3 src1_sel:BYTE_3"
+            : "+v"(f) : "v"(m));
+        break;
+    }
+    return f;
+}
+
 // Metropolis update of one int8x4 word Sv: four spins (bytes +-1), each with
 // its six neighbour spins in bytes of the same position of Xa, Xs, Yp, Ym, Zp,
 // Zm and its six bonds (int32 multiples of 2^-18) in Ja[i] .. Jzn[i].  The four
 // bytes are four sites of one walker (row and HBM engines) or one site of four
 // walkers (group engine).  rw holds byte i's Philox word in word i; cl[i] =
-// neg2beta_log2e(beta32) of byte i's slot and b2_of(i) returns 2 beta32 of that
+// two_beta_log2e(beta32) of byte i's slot and b2_of(i) returns 2 beta32 of that
 // slot (read only on the exact path).  Returns the flip mask (0xFE in the bytes
 // of accepted sites) and S_u of every byte in Sus (S_J = S_u 2^-18).
 //
-// Decision: x = -fl32(beta32 dE) is formed as fl32((-2 beta32 s_i) f) (the same
-// real number, rounded once), dE <= 0 iff x >= 0, exp_ea32 is 0 below -86.  The
-// random word is decided by the sign of the gap g = fl32(W - 2^(y + 32)),
-// y = fl32((-fl32(2 beta32 log2 e) s_i) f), when |g| > M (accept_gap;
-// ea_verify_exp_bracket proves both signs safe for every binary32 x), otherwise
-// by x >= 0 or U 2^-24 < exp_ea32(x), the contract's rule itself.
+// Decision: with f = fl32(S_J + h) and g = -s_i f (exact), x = -fl32(beta32 dE)
+// is fl32(2 beta32 g) (the same real number, rounded once), dE <= 0 iff x >= 0,
+// exp_ea32 is 0 below -86.  The random word is decided by the sign of the gap
+// fl32(W - 2^(y + 32)), y = fl32(fl32(2 beta32 log2 e) g), when its magnitude
+// exceeds M (accept_gap; ea_verify_exp_bracket proves both signs safe for every
+// binary32 x), otherwise by x >= 0 or U 2^-24 < exp_ea32(x), the contract's rule.
 template <class B2>
 __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, uint32_t Xs, uint32_t Yp,
                                                       uint32_t Ym, uint32_t Zp, uint32_t Zm, const int Ja[4],
@@ -30,7 +55,7 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
                                                       const float cl[4], B2 b2_of, float h32, int Sus[4])
 {
     const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
-    const uint32_t nS = ~Sv;  // byte sign bit set iff s_i = +1
+    const uint32_t up = ~Sv & 0x80808080u;  // 0x80 in the bytes with s_i = +1
     uint32_t fm = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -44,22 +69,14 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
         Sus[i] = Su;
         // f = fl32(S_J + h): S_J = Su 2^-18 exactly, so the fused form rounds once, as the sum does
         const float f = __builtin_fmaf((float)Su, 0x1p-18f, h32);
-        // the sign of -2 beta32 s_i: set iff s_i = +1
-        const uint32_t cb = __builtin_amdgcn_ubfe(nS, sh + 7, 1) << 31 | (__float_as_uint(cl[i]) & 0x7FFFFFFFu);
-        const float y = __uint_as_float(cb) * f;  // ~ x log2(e)
-        const float g = accept_gap(y, (float)words[i]);
-        const bool sure = g < -ACCEPT_MARGIN, maybe = g <= ACCEPT_MARGIN;  // sure implies maybe
+        const float g = flip_by_byte(f, up, i);  // -s_i f
+        const float gap = accept_gap(cl[i] * g, (float)words[i]);
+        const bool sure = gap < -ACCEPT_MARGIN, maybe = gap <= ACCEPT_MARGIN;  // sure implies maybe
         bool accept = sure;
-        // If a lane of the wave has |g| <= M (the two lane masks differ),
+        // If a lane of the wave has |gap| <= M (the two lane masks differ),
         // every lane takes the exact test, which the gap only anticipates.
         if (__builtin_amdgcn_ballot_w64(maybe) != __builtin_amdgcn_ballot_w64(sure)) {
-            // the sign is taken again from the spin word (the empty asm keeps the
-            // compiler from sharing it with the main path, whose shift-and-merge
-            // of c' then stays one instruction)
-            uint32_t ns = nS;
-            asm volatile("" : "+v"(ns));
-            const uint32_t c = __builtin_amdgcn_ubfe(ns, sh + 7, 1) << 31 | __float_as_uint(b2_of(i));
-            const float x = __uint_as_float(c) * f;  // = -fl32(beta dE)
+            const float x = b2_of(i) * g;  // = -fl32(beta dE)
             accept = x >= 0.0f || (float)(words[i] >> 8) * 0x1p-24f < exp_ea32(x);
         }
         fm |= accept ? 0xFEu << sh : 0u;
