@@ -113,12 +113,12 @@ __device__ __forceinline__ double exp_ea64(double x)
     return x < -700.0 ? 0.0 : v;
 }
 
-// Acceptance gap.  The engines form the exponent y = fl32(c' g) with g = -s_i f
-// (exact) and the per-slot constant c' = fl32(2 beta32 log2 e), so
-// y = x log2(e) (1 + e), |e| < 3.01 2^-24, for x = fl32(2 beta32 g) =
-// -fl32(beta32 dE) (three roundings: c', y, x), and the hardware estimate
-// a = 2^y of exp_ea32(x).  With W = fl32(w) for the 32-bit random word w (so
-// |W - w| <= 128), U = w >> 8 the 24-bit uniform numerator, A = a 2^32,
+// Acceptance gap.  The engines form an exponent y that estimates x log2(e),
+// x = -fl32(beta32 dE), from the per-slot constant c' = fl32(2 beta32 log2 e)
+// (update_word_gauss gives the two forms and their rounding bound), and the
+// hardware estimate a = 2^y of exp_ea32(x).  With W = fl32(w) for the 32-bit
+// random word w (so |W - w| <= 128), U = w >> 8 the 24-bit uniform numerator,
+// A = a 2^32,
 // T = exp_ea32(x) 2^32 and the gap g = fl32(W - A) (one fused rounding):
 //   g < -M  =>  W - A < -M  =>  U <= w/256 < (A - M + 128)/256,
 //   g >  M  =>  W - A >  M  =>  U >  w/256 - 1 > (A + M - 384)/256,
@@ -126,9 +126,9 @@ __device__ __forceinline__ double exp_ea64(double x)
 // g > M a correct reject.  ea_verify_exp_bracket checks, for every binary32 x,
 // that pair of inequalities (T = 0 below -86; for x > 0, where the exact test
 // accepts, only A >= 2^32 - M + 384, so that g > M cannot happen) at both ends
-// of the range of a over every y within a relative 2^-21 of x log2(e), using
-// that the hardware exponential is monotone (checked on every binary32 input
-// by the same call).  Inside [-M, M] the exact test decides.
+// of the range of a over every y within a relative 2^-21 of x log2(e) plus
+// 2^-20, using that the hardware exponential is monotone (checked on every
+// binary32 input by the same call).  Inside [-M, M] the exact test decides.
 constexpr float ACCEPT_MARGIN = 8192.0f;  // M
 
 // c' of a slot: fl32(2 beta32 log2 e), one rounding (2 beta32 is exact).

@@ -115,8 +115,9 @@ __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &
             const int Jy[4] = {jy, jy, jy, jy}, Jyn[4] = {jym, jym, jym, jym};
             const int Jz[4] = {jz, jz, jz, jz}, Jzn[4] = {jzm, jzm, jzm, jzm};
             // the exact path reads 2 beta32 of walker i's slot, t = bits 1 .. 27 of its counter word
-            fm = update_word_gauss(Sv, X[0], X[1], X[2], X[3], X[4], X[5], Ja, Js, Jy, Jyn, Jz, Jzn, rk, ln.cl,
-                                   [&](int i) { return 2.0f * b32[(ln.c2[i] >> 1) & 0x7FFFFFFu]; }, ln.h32, Sus) &
+            fm = update_word_gauss<false>(Sv, X[0], X[1], X[2], X[3], X[4], X[5], Ja, Js, Jy, Jyn, Jz, Jzn, rk,
+                                          ln.cl, ln.cl, [&](int i) { return 2.0f * b32[(ln.c2[i] >> 1) & 0x7FFFFFFu]; },
+                                          ln.h32, 0, Sus) &
                  ln.valid;
         } else {
             // bond-spin product bytes J s_j: 0x01 (+1) or 0xFF (-1); c counts the -1

@@ -195,6 +195,8 @@ ea_status validate(const ea_desc *d)
             if (!std::isfinite(b) || b <= 0.0) return fail(EA_EINVAL, "sample %d: beta[%d] not finite and > 0", s, t);
             if (t > 0 && b < d->beta[boff + t - 1])
                 return fail(EA_EINVAL, "sample %d: beta must be non-decreasing", s);
+            if (d->jkind == EA_J_GAUSS_F32 && b > 1048576.0)
+                return fail(EA_EINVAL, "sample %d: beta[%d] above 2^20 (Gaussian couplings)", s, t);
         }
         const int64_t N = (int64_t)L * L * L;
         for (int64_t i = 0; i < 3 * N; ++i) {
@@ -419,6 +421,15 @@ int row_threads(int L, int nT)
 bool row_engine(int L, int nT, int jk)
 {
     return jk == 0 && (L == 8 || L == 16) && row_threads(L, nT) <= ROW_MAX_THREADS;
+}
+
+// The field's nearest point on the coupling grid, round(h 2^18), kept within
+// +-6 2^21 (beyond the largest |S_J| 2^18): the engines add it to the integer
+// local field and carry only the remainder h - hgrid 2^-18 in binary32.
+int32_t field_grid(float h)
+{
+    const double g = std::nearbyint((double)h * 262144.0), lim = 6.0 * 2097152.0;
+    return (int32_t)std::max(-lim, std::min(lim, g));
 }
 
 // +-1 couplings: bit a*7+b of the mask is set iff dE = 2 s (S_J + h) <= 0 for
@@ -757,7 +768,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         const SampleHost &h = e->smp[s];
         const int N = h.N, HALF = N / 2;
         sd[s] = SampleDev{h.L, h.nT, h.id, h.h, h.spin_off, h.J_off, h.slot_off, h.hbm ? 1 : 0, h.frame_off,
-                          down_mask_of(h.h), 0, h.jb_off};
+                          down_mask_of(h.h), field_grid(h.h), h.jb_off};
         items[e->item_pos[s]] = 2 * s;
         items[e->item_pos[s] + 1] = 2 * s + 1;
         for (int t = 0; t < h.nT; ++t) {

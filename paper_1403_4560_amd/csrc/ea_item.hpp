@@ -33,6 +33,22 @@ __device__ __forceinline__ void block_copy(void *__restrict__ dst, const void *_
     }
 }
 
+// count walkers of bytes each (a multiple of 8) from consecutive blocks at
+// glob to blocks lstride bytes apart at lds (to_lds), or back, in 8-byte words.
+__device__ __forceinline__ void copy_walkers(int8_t *lds, size_t lstride, int8_t *glob, int count, size_t bytes,
+                                             bool to_lds)
+{
+    const int T = blockDim.x, tid = threadIdx.x;
+    const size_t per = bytes / 8, total = per * (size_t)count;
+    for (size_t i = tid; i < total; i += T) {
+        const size_t w = i / per, j = i - w * per;
+        uint2 *l = (uint2 *)(lds + w * lstride) + j;
+        uint2 *g = (uint2 *)(glob + w * bytes) + j;
+        if (to_lds) *l = *g;
+        else *g = *l;
+    }
+}
+
 __device__ __forceinline__ long long wave_sum_i64(long long v)
 {
 #pragma unroll

@@ -59,8 +59,8 @@ __device__ __forceinline__ void site_half_sweep(const SweepArgs &A, const Sample
             const u32x4 rw = philox4x32_10((uint32_t)g, c1, c2base | ((uint32_t)t << 1), d.sample_id,
                                            A.key0, A.key1);
             const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
-            int8_t *Sp = I.S + (size_t)w * N + p * HALF;
-            const int8_t *So = I.S + (size_t)w * N + (1 - p) * HALF;
+            int8_t *Sp = I.S + (size_t)w * item_walker_stride(L) + p * HALF;
+            const int8_t *So = I.S + (size_t)w * item_walker_stride(L) + (1 - p) * HALF;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int h = 4 * g + i;
@@ -196,8 +196,8 @@ struct RowMap {
 template <int L, int P, int EPS>
 __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d, uint8_t *Sw, const int *J,
                                          int o_y0, int o_yp, int o_ym, int o_x, int e_prev, int z, int zp,
-                                         int zm, uint32_t c1, uint32_t c2, float cl, float h32, int &accE, int &nd,
-                                         int &bf, int &bd)
+                                         int zm, uint32_t c1, uint32_t c2, float ka, float kb, float h32,
+                                         int &accE, int &nd, int &bf, int &bd)
 {
     constexpr int HALF = L * L * L / 2, HL = L / 2, PLANE = L * HL;
     const uint8_t *own = Sw + P * HALF, *oth = Sw + (1 - P) * HALF;
@@ -231,11 +231,11 @@ __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d,
     const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
     const uint32_t g = (uint32_t)(o_y0 / 4 + z * (PLANE / 4));
     const u32x4 rw = philox4x32_10(g, c1, c2, d.sample_id, A.key0, A.key1);
-    const float clv[4] = {cl, cl, cl, cl};
+    const float kav[4] = {ka, ka, ka, ka}, kbv[4] = {kb, kb, kb, kb};
     int Sus[4];
-    const uint32_t fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, clv,
-                                          [&](int) { return 2.0f * A.beta32[d.slot_off + ((c2 >> 1) & 0x7FFFFFFu)]; },
-                                          h32, Sus);
+    const uint32_t fm = update_word_gauss<true>(
+        Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, kav, kbv,
+        [&](int) { return 2.0f * A.beta32[d.slot_off + ((c2 >> 1) & 0x7FFFFFFu)]; }, h32, d.hgrid, Sus);
     if constexpr (P == 1) tally_final(Sv, fm, Sus, accE, nd);
     *(uint32_t *)(Sw + P * HALF + o_y0 + zo) = Sv ^ fm;
     bf += __builtin_popcount(fm);
@@ -254,21 +254,21 @@ __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleD
     const int o_y0 = 4 * (y * WPR + k), o_yp = 4 * (yp * WPR + k), o_ym = 4 * (ym * WPR + k);
     const int o_x = 4 * (y * WPR + kx);
     const int e_prev = y * HL + (k == 0 ? HL - 1 : 4 * k - 1);  // element before the word, cyclic
-    uint8_t *Sw = (uint8_t *)I.S + (size_t)w * N;
+    uint8_t *Sw = (uint8_t *)I.S + (size_t)w * item_walker_stride(L);
     const int *J = (const int *)I.J;
     const uint32_t c1 = (uint32_t)(2 * n + P);
     const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
-    const float cl = two_beta_log2e(I.b32[t]);
-    // the field in a vector register: every site's fused add takes it there
-    float h32 = d.h32;
-    asm volatile("" : "+v"(h32));
+    // the exponent's two per-slot constants (see update_word_gauss)
+    const float cp = two_beta_log2e(I.b32[t]);
+    const float ka = cp * 0x1p-18f, kb = cp * (d.h32 - (float)d.hgrid * 0x1p-18f);
+    float h32 = d.h32;  // exact path only
 #pragma unroll 1
     for (int z = 0; z < L; z += 2) {
         const int zm = z == 0 ? L - 1 : z - 1, zpp = z + 2 == L ? 0 : z + 2;
-        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z, z + 1, zm, c1, c2, cl, h32, accE, nd,
-                           bf, bd);
-        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, zpp, z, c1, c2, cl, h32, accE,
-                               nd, bf, bd);
+        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z, z + 1, zm, c1, c2, ka, kb, h32, accE,
+                           nd, bf, bd);
+        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, zpp, z, c1, c2, ka, kb, h32,
+                               accE, nd, bf, bd);
     }
 }
 
@@ -300,7 +300,7 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
 
     const size_t sbase = (size_t)d.spin_off + (size_t)r * nT * N;
     const int gi = 2 * d.slot_off + r * nT;
-    block_copy(I.S, A.spins + sbase, (size_t)nT * N);
+    copy_walkers(I.S, item_walker_stride(L), A.spins + sbase, nT, N, true);
     if constexpr (ROW) {
         // couplings as exact int32 multiples of 2^-18
         const float4 *src = (const float4 *)((const float *)A.J + d.J_off);  // J_off is a multiple of 4
@@ -364,8 +364,10 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
             if (on) {
                 if (rw_par) row_half_sweep<L, 1, 0>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, nd, bf, bd);
                 else row_half_sweep<L, 1, 1>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, nd, bf, bd);
-                // |accE| <= 64 sites x 6 (2^21 - 1) < 2^31 per thread
-                const long long sE = group_sum_i64<CPW>((long long)accE + nd);
+                // accE + nd = sum of s' (S_u + hgrid) over this thread's 4 L odd
+                // sites, |accE| <= 64 sites x 12 2^21 < 2^31; less hgrid sum s'
+                const long long sE =
+                    group_sum_i64<CPW>((long long)accE + nd - (long long)d.hgrid * (4 * L - 2 * nd));
                 const int sf = group_sum_i32<CPW>(bf), sd = group_sum_i32<CPW>(bd);
                 if (rw_rem == 0) {
                     const int flips = sf / 7, ndown = sd / 7;
@@ -396,7 +398,7 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
             uint32_t *dst = A.frames + f * A.frame_words + d.frame_off + (size_t)r * nT * L * L;
             for (int i = tid; i < nT * L * L; i += T) {
                 const int t = i / (L * L), row = i - t * (L * L);
-                dst[i] = pack_row_lds<L>(I.S + (size_t)I.was[t] * N, row);
+                dst[i] = pack_row_lds<L>(I.S + (size_t)I.was[t] * item_walker_stride(L), row);
             }
             for (int t = tid; t < nT; t += T) {
                 const int w = I.was[t];
@@ -405,7 +407,7 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
         }
     }
     __syncthreads();
-    block_copy(A.spins + sbase, I.S, (size_t)nT * N);
+    copy_walkers(I.S, item_walker_stride(L), A.spins + sbase, nT, N, false);
     for (int i = tid; i < nT; i += T) {
         A.was[gi + i] = I.was[i];
         A.EJ[gi + i] = I.EJ[i];
@@ -524,7 +526,8 @@ __global__ void __launch_bounds__(256) hbm_half_kernel(SweepArgs A)
     const uint32_t c1 = (uint32_t)(2 * n + p);
     const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
     const float b32 = A.beta32[d.slot_off + t];
-    const float cl = two_beta_log2e(b32);
+    const float cp = two_beta_log2e(b32);
+    const float ka = cp * 0x1p-18f, kb = cp * (d.h32 - (float)d.hgrid * 0x1p-18f);
     int accE = 0, bf = 0, bd = 0;
     for (int j = 0; j < (TILE + 255) / 256; ++j) {
         const int g = tile * TILE + j * 256 + tid;
@@ -561,10 +564,10 @@ __global__ void __launch_bounds__(256) hbm_half_kernel(SweepArgs A)
             const int Js[4] = {eps ? Jpx.x : Ep, eps ? Jpx.y : V.x, eps ? Jpx.z : V.y, eps ? Jpx.w : V.z};
             const int Jy[4] = {Jpy.x, Jpy.y, Jpy.z, Jpy.w}, Jyn[4] = {Jym.x, Jym.y, Jym.z, Jym.w};
             const int Jz[4] = {Jpz.x, Jpz.y, Jpz.z, Jpz.w}, Jzn[4] = {Jzm.x, Jzm.y, Jzm.z, Jzm.w};
-            const float clv[4] = {cl, cl, cl, cl};
+            const float kav[4] = {ka, ka, ka, ka}, kbv[4] = {kb, kb, kb, kb};
             int Sus[4];
-            fm = update_word_gauss(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, clv,
-                                   [=](int) { return 2.0f * b32; }, d.h32, Sus);
+            fm = update_word_gauss<true>(Sv, Xa, Xs, Yp, Ym, Zp, Zm, Ja, Js, Jy, Jyn, Jz, Jzn, rw, kav, kbv,
+                                         [=](int) { return 2.0f * b32; }, d.h32, d.hgrid, Sus);
             accE += tally_delta(Sv, fm, Sus);
         } else {
             const uint8_t *J8 = (const uint8_t *)A.J + d.J_off;
@@ -589,7 +592,9 @@ __global__ void __launch_bounds__(256) hbm_half_kernel(SweepArgs A)
     block_sum3<256>(sE, bf, bd);
     if (tid == 0) {
         const int flips = bf / 7, ndown = bd / 7;
-        atomicAdd((unsigned long long *)&A.dEJ[gi + w], (unsigned long long)(2 * (sE + ndown)));
+        // sE + ndown = sum over accepted sites of s (S_u + hgrid) (Gaussian), less hgrid sum s
+        const long long corr = JK == 0 ? (long long)d.hgrid * (flips - 2 * ndown) : 0;
+        atomicAdd((unsigned long long *)&A.dEJ[gi + w], (unsigned long long)(2 * (sE + ndown - corr)));
         atomicAdd(&A.dM[gi + w], -2 * (flips - 2 * ndown));
         atomicAdd((unsigned long long *)&A.flips[gi + t], (unsigned long long)flips);
     }
@@ -880,8 +885,10 @@ __device__ __forceinline__ float float_down(float v) { return -float_up(-v); }
 // pattern v (NaNs excluded by the launch):
 // (1) the hardware exponential is monotone: 2^v <= 2^(next binary32 above v);
 // (2) for x = v: every exponent y the engines can form for x lies within a
-//     relative 2^-21 (eight times the rounding bound) of z = x log2(e), plus
-//     2^-140 for subnormal rounding; with yl, yh the binary32 values just
+//     relative 2^-21 of z = x log2(e) plus an absolute 2^-20 (the roundings of
+//     both forms in update_word_gauss: at most about 5 2^-24 relative, plus
+//     2 beta32 log2(e) 2^-19 2^-24 < 2^-20 from the field remainder's constant
+//     of the folded form for beta32 <= 2^20); with yl, yh the binary32 values just
 //     outside that interval and A = 2^y 2^32 at both ends (exact here),
 //     T = exp_ea32(x) 2^32 (0 below -86):
 //       x <= 0:  T - (M - 384) <= A(yl)  and  A(yh) <= T + (M - 128)
@@ -898,7 +905,7 @@ __global__ void exp_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned
 
     const double TWO32 = 4294967296.0, M = ACCEPT_MARGIN;
     const double z = (double)v * (double)__uint_as_float(0x3FB8AA3Bu);  // exact: 24 x 24 bits
-    const double B = 0x1p-21, D = 0x1p-140;
+    const double B = 0x1p-21, D = 0x1p-20;
     const double zl = (z <= 0.0 ? z * (1.0 + B) : z * (1.0 - B)) - D;
     const double zh = (z <= 0.0 ? z * (1.0 - B) : z * (1.0 + B)) + D;
     float yl = (float)zl, yh = (float)zh;

@@ -49,7 +49,7 @@ struct SampleDev {
     int32_t tier;       // 0 = LDS-resident, 1 = HBM-resident
     int64_t frame_off;  // words into each snapshot frame
     uint32_t down_mask; // +-1 couplings: bit a*7+b set iff 2 s (S_J + h) <= 0, s = 2a-1, S_J = 2b-6
-    int32_t pad;
+    int32_t hgrid;      // Gaussian couplings: the field on the 2^-18 grid, round(h 2^18) within +-6 2^21
     int64_t jb_off;     // bit engine: words into Jbits
 };
 
@@ -124,13 +124,19 @@ struct LdsOff {
     size_t spins, J, was, sow, M, dM, fl, sw, EJ, dEJ, lut, b32, b64, total;
 };
 
+// Bytes between consecutive walkers of the per-item frame's LDS spins: N plus
+// 8.  The row engine's wave holds the same columns of four walkers, whose words
+// fall two words (mod 4) apart, so the two walkers of each half-wave read
+// disjoint LDS banks.
+__host__ __device__ inline size_t item_walker_stride(int L) { return (size_t)L * L * L + 8; }
+
 __host__ __device__ inline LdsOff lds_offsets(int L, int nT, int jkind)
 {
     const size_t N = (size_t)L * L * L;
     const size_t T4 = (size_t)((nT + 3) & ~3);
     LdsOff o;
     o.spins = 0;
-    o.J = align16((size_t)nT * N);
+    o.J = align16((size_t)nT * item_walker_stride(L));
     o.was = o.J + align16(3 * N * (jkind == 0 ? 4 : 1));
     o.sow = o.was + 4 * T4;
     o.M = o.sow + 4 * T4;

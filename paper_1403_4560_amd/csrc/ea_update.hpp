@@ -36,23 +36,31 @@ __device__ __forceinline__ float flip_by_byte(float f, uint32_t m, int i)
 // its six neighbour spins in bytes of the same position of Xa, Xs, Yp, Ym, Zp,
 // Zm and its six bonds (int32 multiples of 2^-18) in Ja[i] .. Jzn[i].  The four
 // bytes are four sites of one walker (row and HBM engines) or one site of four
-// walkers (group engine).  rw holds byte i's Philox word in word i; cl[i] =
-// two_beta_log2e(beta32) of byte i's slot and b2_of(i) returns 2 beta32 of that
-// slot (read only on the exact path).  Returns the flip mask (0xFE in the bytes
-// of accepted sites) and S_u of every byte in Sus (S_J = S_u 2^-18).
+// walkers (group engine).  rw holds byte i's Philox word in word i; b2_of(i)
+// returns 2 beta32 of byte i's slot (read only on the exact path).  Returns
+// the flip mask (0xFE in the bytes of accepted sites) and the integer local
+// field of every byte in Sus: S_u (S_J = S_u 2^-18), or with FOLD S_u + hgrid.
 //
 // Decision: with f = fl32(S_J + h) and g = -s_i f (exact), x = -fl32(beta32 dE)
 // is fl32(2 beta32 g) (the same real number, rounded once), dE <= 0 iff x >= 0,
 // exp_ea32 is 0 below -86.  The random word is decided by the sign of the gap
-// fl32(W - 2^(y + 32)), y = fl32(fl32(2 beta32 log2 e) g), when its magnitude
-// exceeds M (accept_gap; ea_verify_exp_bracket proves both signs safe for every
-// binary32 x), otherwise by x >= 0 or U 2^-24 < exp_ea32(x), the contract's rule.
-template <class B2>
+// fl32(W - 2^(y + 32)) when its magnitude exceeds M (accept_gap), otherwise by
+// x >= 0 or U 2^-24 < exp_ea32(x), the contract's rule.  The exponent y
+// estimates x log2(e):
+//   FOLD = false: y = fl32(c' g), ka[i] = c' = two_beta_log2e(beta32);
+//   FOLD = true:  y = -s_i fl32(fl32(S_u + hgrid) ka[i] + kb[i]) with
+//     ka[i] = c' 2^-18 and kb[i] = fl32(c' (h - hgrid 2^-18)), one fused
+//     operation for the field and the temperature together.
+// ea_verify_exp_bracket proves both signs of the gap safe for every binary32 x
+// and every y the two forms can produce (within a relative 2^-21 of x log2(e)
+// plus 2^-20; the bound on the second form needs beta32 <= 2^20).
+template <bool FOLD, class B2>
 __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, uint32_t Xs, uint32_t Yp,
                                                       uint32_t Ym, uint32_t Zp, uint32_t Zm, const int Ja[4],
                                                       const int Js[4], const int Jy[4], const int Jyn[4],
                                                       const int Jz[4], const int Jzn[4], const u32x4 rw,
-                                                      const float cl[4], B2 b2_of, float h32, int Sus[4])
+                                                      const float ka[4], const float kb[4], B2 b2_of, float h32,
+                                                      int hgrid, int Sus[4])
 {
     const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
     const uint32_t up = ~Sv & 0x80808080u;  // 0x80 in the bytes with s_i = +1
@@ -66,16 +74,30 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
         Su += __mul24(__builtin_amdgcn_sbfe((int)Ym, sh, 8), Jyn[i]);
         Su += __mul24(__builtin_amdgcn_sbfe((int)Zp, sh, 8), Jz[i]);
         Su += __mul24(__builtin_amdgcn_sbfe((int)Zm, sh, 8), Jzn[i]);
+        if constexpr (FOLD) Su += hgrid;
         Sus[i] = Su;
-        // f = fl32(S_J + h): S_J = Su 2^-18 exactly, so the fused form rounds once, as the sum does
-        const float f = __builtin_fmaf((float)Su, 0x1p-18f, h32);
-        const float g = flip_by_byte(f, up, i);  // -s_i f
-        const float gap = accept_gap(cl[i] * g, (float)words[i]);
+        float g, y;
+        if constexpr (FOLD) {
+            y = flip_by_byte(__builtin_fmaf((float)Su, ka[i], kb[i]), up, i);
+        } else {
+            // f = fl32(S_J + h): S_J = Su 2^-18 exactly, so the fused form rounds once, as the sum does
+            g = flip_by_byte(__builtin_fmaf((float)Su, 0x1p-18f, h32), up, i);  // -s_i f
+            y = ka[i] * g;
+        }
+        const float gap = accept_gap(y, (float)words[i]);
         const bool sure = gap < -ACCEPT_MARGIN, maybe = gap <= ACCEPT_MARGIN;  // sure implies maybe
         bool accept = sure;
         // If a lane of the wave has |gap| <= M (the two lane masks differ),
         // every lane takes the exact test, which the gap only anticipates.
         if (__builtin_amdgcn_ballot_w64(maybe) != __builtin_amdgcn_ballot_w64(sure)) {
+            if constexpr (FOLD) {
+                // S_u taken back from S_u + hgrid here only (the empty asm keeps
+                // the compiler from holding the sum without hgrid for this path,
+                // which would cost the main path a separate add)
+                int su = Su;
+                asm volatile("" : "+v"(su));
+                g = flip_by_byte(__builtin_fmaf((float)(su - hgrid), 0x1p-18f, h32), up, i);
+            }
             const float x = b2_of(i) * g;  // = -fl32(beta dE)
             accept = x >= 0.0f || (float)(words[i] >> 8) * 0x1p-24f < exp_ea32(x);
         }

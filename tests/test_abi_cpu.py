@@ -125,3 +125,11 @@ def test_rejects_unknown_tier(small):
     d, keep = _desc(small, tier=4)
     st, h, msg = _create(d)
     assert st == -1 and not h.value and "tier" in msg
+
+
+def test_rejects_beta_beyond_the_acceptance_bound(small):
+    b = small.beta.copy()
+    b[-1] = 2.0 ** 21
+    d, keep = _desc(small, beta=b)
+    st, h, msg = _create(d)
+    assert st == -1 and not h.value and "2^20" in msg
