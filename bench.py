@@ -54,14 +54,16 @@ WORKLOAD_TEXT = {
 #     word 2 product and xor of round 0 and the word 0 product of round 1 = 37
 #   shifted x-neighbour word (one byte permute)                        =  1
 #   per site, Gaussian couplings: 6 byte-select multiplies and 3 adds for
-#     S_u, conversion and + h (2), the sign of -2 beta s_i (1.75), x (1),
-#     hardware exponential estimate (2), bracket bounds (2), word to
-#     float (1), two compares (2), flip byte (1)          = 21.75 x 4 = 87
+#     S_u plus the field's grid part, conversion (1), one fused operation for
+#     the temperature and the field remainder (1), the spin's sign (1),
+#     hardware exponential (1), word to float (1), the acceptance gap (1),
+#     two compares (2), flip byte (1)                          = 19 x 4 = 76
+#   the word's spin-sign mask (1)                                      =  1
 #   word tail: flip-mask merge (2), new spins (1), flip and down-flip
 #     counts (3)                                                      =  6
 #   energy, second half-sweep only: per site sign-extend and xor (2), two
 #     adds per word, down count (2): 12 per word, 6 on average        =  6
-# Gaussian: (37 + 1 + 87 + 6 + 6) / 4 = 34.25.
+# Gaussian: (37 + 1 + 76 + 1 + 6 + 6) / 4 = 31.75.
 # +-1 couplings, one bit per spin, per 32-site word / 32:
 #   Philox 8 x 37 = 296; per site: table address (1), compare and carry-in
 #   (2) = 96; class bytes: 3 spread-table addresses (2 each) and 4 merges per
@@ -70,7 +72,7 @@ WORKLOAD_TEXT = {
 #   (3), new spins (1), flip and down-flip counts (3), energy on the second
 #   half only (7, 3.5 on average) = 42.5: 474.5 / 32 = 14.83.
 BYTE_PM1_OPS_PER_ATTEMPT = 25.5
-ALG_OPS_PER_ATTEMPT = {"L16_gauss": 34.25, "L8_gauss": 34.25, "mixed_L6_12": 34.25, "L4_gauss": 34.25,
+ALG_OPS_PER_ATTEMPT = {"L16_gauss": 31.75, "L8_gauss": 31.75, "mixed_L6_12": 31.75, "L4_gauss": 31.75,
                        "L32_pm1": 474.5 / 32}
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = non-packed VALU lane-instructions/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -79,9 +81,10 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the factors a plain copy of
 # known size reads), keyed by a fingerprint of the kernel sources they were
 # taken on; reported as null once the kernels change.
-MEASURED_TRAFFIC = {"L16_gauss": ("2442795888009521", 2.1074e9), "L32_pm1": ("2442795888009521", 3.5385e9)}
+MEASURED_TRAFFIC = {"L16_gauss": ("17226a4c8751d156", 2.0321e9), "L32_pm1": ("17226a4c8751d156", 3.5369e9)}
 KERNEL_SOURCES = tuple("paper_1403_4560_amd/csrc/" + f for f in (
-    "ea_kernels.hip", "ea_bits.hip", "ea_group.hip", "ea_item.hpp", "ea_update.hpp", "ea_device.hpp"))
+    "ea_kernels.hip", "ea_bits.hip", "ea_group.hip", "ea_item.hpp", "ea_update.hpp", "ea_device.hpp",
+    "ea_types.hpp"))
 
 
 def kernel_fingerprint():

@@ -77,7 +77,9 @@ typedef struct {
     const uint32_t *sample_id;   /* [S] Philox address word 3; NULL => 0..S-1   */
     const int32_t *L;            /* [S] even, 2 <= L <= 32                      */
     const int32_t *n_temps;      /* [S] 1 <= n_T <= 64                          */
-    const double *beta;          /* concat [S][n_T]: finite, > 0, non-decreasing */
+    const double *beta;          /* concat [S][n_T]: finite, > 0, non-decreasing;
+                                    <= 2^20 with Gaussian couplings (the
+                                    acceptance shortcut's error bound) */
     const float *h;              /* [S] uniform field, finite                    */
     int32_t jkind;               /* EA_J_GAUSS_F32 or EA_J_PM1_I8                */
     const void *J;               /* concat [S][3][N]: float on the 2^-18 grid
