@@ -93,6 +93,19 @@ def test_pm1_couplings_lds_tier(torch_cuda):
     check(work, 40, tier=2)  # the byte engine at L = 8 too
 
 
+def test_fields_and_temperatures_at_the_exponent_bounds(torch_cuda):
+    # The row and HBM engines split the field into its point on the coupling
+    # grid (added to the integer local field, within +-48) and a binary32
+    # remainder: a field on the grid (remainder 0), a tiny one, one just inside
+    # the grid part's clamp and three beyond it, both signs; temperatures down to
+    # 0.002 (beta = 500).  The group engine (L = 6, 10) takes the same fields.
+    work = W.make_workload([8, 16, 8, 8, 16, 6, 10, 8], [4, 6, 5, 3, 4, 6, 4, 4], (0.002, 2.0),
+                           [0.5, 60.0, -55.0, 47.99, 1e-7, -50.0, 49.0, -0.375], measure_every=4,
+                           measure_start=8, name="field bounds")
+    check(work, 40)
+    check(work.subset([0, 1, 2, 3, 4, 7]), 24, tier=1)  # the HBM tier's half-sweep kernel
+
+
 def test_degenerate_sizes(torch_cuda):
     # L = 2 (every neighbour pair joined by two bonds), one temperature (no
     # exchange), an odd number of temperatures, L = 14
