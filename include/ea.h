@@ -226,6 +226,28 @@ ea_status ea_synchronize(ea_ensemble *ens);
 ea_status ea_query(const ea_ensemble *ens, int32_t *n_samples, int64_t *total_slots,
                    int64_t *device_bytes);
 
+/* Device bytes of the persistent buffers an ensemble created from desc would
+ * hold (samples, couplings, spins, temperatures, walker maps, energies,
+ * counters, accumulators, tables), laid out as one arena of 256-byte aligned
+ * slices: the size of the caller memory ea_bind_buffers takes.  The snapshot
+ * frames (sized by the plan's chunk) and the scratch of ea_check_energies are
+ * not part of it and stay library-owned.  Validates desc as
+ * ea_create_ensemble does and asks the current device for its LDS size (which
+ * decides the engines); allocates nothing.  EA_EDEVICE without a device. */
+ea_status ea_query_sizes(const ea_desc *desc, size_t *device_bytes);
+
+/* Move the ensemble's persistent buffers into caller-owned device memory, for
+ * callers that account memory themselves (a torch tensor, say).
+ * device_ptrs[0] is the arena: arena_bytes (at least ea_query_sizes bytes) of
+ * device memory of the ensemble's device, 256-byte aligned, left untouched by
+ * the caller while the ensemble lives.  The current contents are copied over
+ * (synchronizing the stream) and the library's own buffers freed; from then on
+ * the library reads and writes the arena and never frees it (ea_destroy
+ * leaves it to the caller).  Results are the same as without binding.
+ * EA_EINVAL for a NULL, misaligned or too small arena (checked against the
+ * allocation that holds it), EA_ESTATE if already bound. */
+ea_status ea_bind_buffers(ea_ensemble *ens, void *const *device_ptrs, size_t arena_bytes);
+
 /* The engine that runs each sample's sweeps (chosen at creation from L, n_T,
  * the coupling kind, the field, the LDS size and the tier option).
  * engines_host [S] (caller-owned) receives one ea_engine value per sample. */
@@ -239,15 +261,18 @@ enum {
 ea_status ea_query_engines(const ea_ensemble *ens, int32_t *engines_host);
 
 /* Device self-check of the acceptance shortcut used by the sweep kernels.
- * The kernels estimate a = 2^(x log2 e) with the hardware exponential and form
- * the gap g = fl32(fl32(w) - a 2^32) for the random word w; g < -8192 accepts
- * and g > 8192 rejects without evaluating the in-house exp_ea32, any other
- * word takes the exact test (x >= 0 or U 2^-24 < exp_ea32(x), U = w >> 8).
- * This call checks, over every non-NaN binary32 x (4.3e9 values), the bounds
- * on a that make both shortcuts decide as the exact test would for every w:
- * for x <= 0 that a 2^32 lies within 8192 - 384 below and 8192 - 128 above
+ * The kernels form an exponent y estimating x log2 e for x = -fl32(beta dE)
+ * (within a relative 2^-21 plus 2^-20, from their roundings), a = 2^y with the
+ * hardware exponential, and the gap g = fl32(fl32(w) - a 2^32) for the random
+ * word w; g < -8192 accepts and g > 8192 rejects without evaluating the
+ * in-house exp_ea32, any other word takes the exact test (x >= 0 or
+ * U 2^-24 < exp_ea32(x), U = w >> 8).  This call checks, over every non-NaN
+ * binary32 x (4.3e9 values) and at both ends of that range of y, the bounds on
+ * a that make both shortcuts decide as the exact test would for every w: for
+ * x <= 0 that a 2^32 lies within 8192 - 384 below and 8192 - 128 above
  * exp_ea32(x) 2^32 (exp_ea32 = 0 below -86), for x > 0 that a 2^32 >=
- * 2^32 - 8192 + 384.  *violations must be 0; *max_rel_dev is the largest
+ * 2^32 - 8192 + 384; and that the hardware exponential is monotone over every
+ * binary32 input.  *violations must be 0; *max_rel_dev is the largest
  * |a/exp_ea32(x) - 1| seen on [-86, 0].  Synchronizing; uses the current
  * device. */
 ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev);

@@ -75,6 +75,8 @@ _SIGS = [
     ("ea_synchronize", ctypes.c_int, [_VP]),
     ("ea_query", ctypes.c_int, [_VP, _VP, _VP, _VP]),
     ("ea_query_engines", ctypes.c_int, [_VP, _VP]),
+    ("ea_query_sizes", ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)]),
+    ("ea_bind_buffers", ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_size_t]),
     ("ea_verify_exp_bracket", ctypes.c_int, [_VP, _VP]),
     ("ea_destroy", None, [_VP]),
     ("ea_last_error", ctypes.c_char_p, []),
@@ -117,6 +119,31 @@ TIER_AUTO, TIER_HBM, TIER_BYTES, TIER_SITE = 0, 1, 2, 3
 ENGINE_NAMES = ["site", "row", "group", "bits", "hbm"]
 
 
+def _desc_of(work, tier=0):
+    """The C descriptor of a workload and the arrays it points into."""
+    keep = dict(
+        sid=np.ascontiguousarray(work.sample_id, dtype=np.uint32),
+        L=np.ascontiguousarray(work.L, dtype=np.int32),
+        nT=np.ascontiguousarray(work.n_temps, dtype=np.int32),
+        beta=np.ascontiguousarray(work.beta, dtype=np.float64),
+        h=np.ascontiguousarray(work.h, dtype=np.float32),
+        J=np.ascontiguousarray(work.J),
+        spins=np.ascontiguousarray(work.spins0, dtype=np.int8))
+    k = keep
+    d = Desc(work.n_samples, _p(k["sid"]).value, _p(k["L"]).value, _p(k["nT"]).value, _p(k["beta"]).value,
+             _p(k["h"]).value, int(work.jkind), _p(k["J"]).value, _p(k["spins"]).value,
+             int(work.seed), int(work.measure_every), int(work.measure_start), int(tier))
+    return d, keep
+
+
+def query_sizes(work, tier=0) -> int:
+    """Bytes of the arena ``Ensemble.bind_buffers`` takes for this workload."""
+    d, keep = _desc_of(work, tier)
+    n = ctypes.c_size_t()
+    _check(load().ea_query_sizes(ctypes.byref(d), ctypes.byref(n)))
+    return n.value
+
+
 class Ensemble:
     """One ensemble of disorder samples on the current HIP device.
 
@@ -130,18 +157,8 @@ class Ensemble:
         lib = load()
         self.work = work
         self.S = work.n_samples
-        self._keep = dict(
-            sid=np.ascontiguousarray(work.sample_id, dtype=np.uint32),
-            L=np.ascontiguousarray(work.L, dtype=np.int32),
-            nT=np.ascontiguousarray(work.n_temps, dtype=np.int32),
-            beta=np.ascontiguousarray(work.beta, dtype=np.float64),
-            h=np.ascontiguousarray(work.h, dtype=np.float32),
-            J=np.ascontiguousarray(work.J),
-            spins=np.ascontiguousarray(work.spins0, dtype=np.int8))
+        d, self._keep = _desc_of(work, tier)
         k = self._keep
-        d = Desc(self.S, _p(k["sid"]).value, _p(k["L"]).value, _p(k["nT"]).value, _p(k["beta"]).value,
-                 _p(k["h"]).value, int(work.jkind), _p(k["J"]).value, _p(k["spins"]).value,
-                 int(work.seed), int(work.measure_every), int(work.measure_start), int(tier))
         h = ctypes.c_void_p()
         _check(lib.ea_create_ensemble(ctypes.byref(d), ctypes.c_void_p(stream) if stream else None,
                                       ctypes.byref(h)))
@@ -282,6 +299,20 @@ class Ensemble:
         s, t, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
         _check(load().ea_query(self._h, ctypes.byref(s), ctypes.byref(t), ctypes.byref(b)))
         return {"n_samples": s.value, "total_slots": t.value, "device_bytes": b.value}
+
+    def bind_buffers(self, arena, nbytes=None):
+        """Move the persistent buffers into caller memory: ``arena`` is a device
+        tensor (kept referenced by the ensemble; its size is passed) or a raw
+        device address with ``nbytes`` given, at least ``query_sizes`` bytes,
+        256-byte aligned."""
+        if hasattr(arena, "data_ptr"):
+            ptr = arena.data_ptr()
+            nbytes = arena.numel() * arena.element_size() if nbytes is None else nbytes
+        else:
+            ptr = int(arena)
+        ptrs = (_VP * 1)(ptr)
+        _check(load().ea_bind_buffers(self._h, ptrs, int(nbytes)))
+        self._arena = arena
 
     def engines(self) -> list:
         """Engine name per sample: site, row, group, bits or hbm."""

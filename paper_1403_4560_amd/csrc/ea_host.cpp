@@ -72,6 +72,7 @@ struct SampleHost {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = true;  // false once bound to caller memory (ea_bind_buffers)
 };
 
 }  // namespace
@@ -122,6 +123,7 @@ struct ea_ensemble {
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
     int64_t device_bytes = 0;
+    bool bound = false;  // persistent buffers live in caller memory
 };
 
 namespace {
@@ -153,9 +155,10 @@ ea_status dalloc(ea_ensemble *e, DevBuf &b, size_t bytes)
 
 void dfree(DevBuf &b)
 {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p && b.owned) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
+    b.owned = true;
 }
 
 int parity(int L, int i) { return (i % L + (i / L) % L + i / (L * L)) & 1; }
@@ -579,6 +582,106 @@ hipError_t enqueue_chunk(ea_ensemble *e, int K, bool unbatched)
     return hipGetLastError();
 }
 
+// Engine choice and offsets of every sample (host only; lds_max is the
+// device's LDS per workgroup), the same for ea_create_ensemble and
+// ea_query_sizes.
+struct SampleTotals {
+    int64_t total_slots = 0, spin_bytes = 0, J_elems = 0, frame_words = 0;
+    int64_t hbm_walkers = 0, jbits_words = 0;
+    bool any_hbm = false;
+};
+
+ea_status plan_samples(const ea_desc *d, size_t lds_max, std::vector<SampleHost> &smp, SampleTotals &tot)
+{
+    const int jk = d->jkind;
+    int64_t soff = 0, joff = 0, foff = 0;
+    int32_t toff = 0;
+    smp.clear();
+    tot = SampleTotals{};
+    for (int s = 0; s < d->n_samples; ++s) {
+        SampleHost h{};
+        h.L = d->L[s];
+        h.nT = d->n_temps[s];
+        h.N = h.L * h.L * h.L;
+        h.id = d->sample_id ? d->sample_id[s] : (uint32_t)s;
+        h.h = d->h[s];
+        h.spin_off = soff;
+        h.J_off = joff;
+        h.slot_off = toff;
+        h.frame_off = foff;
+        const size_t need = lds_offsets(h.L, h.nT, jk).total;
+        const bool fits = h.L <= LDS_MAX_L && need <= lds_max;
+        const bool forced_hbm = d->tier == EA_TIER_HBM && hbm_size(h.L);
+        h.bits = !forced_hbm && d->tier != EA_TIER_BYTES && d->tier != EA_TIER_SITE &&
+                 bits_engine(h.L, h.nT, jk, h.h, lds_max);
+        h.hbm = !h.bits && (!fits || forced_hbm);
+        // the group engine needs a wave's worth of (quad, site group) items;
+        // tinier chains (L = 2, 4) keep the one-site-per-thread engine, which
+        // spreads them over more lanes
+        h.group = !h.hbm && !h.bits && d->tier != EA_TIER_SITE && !row_engine(h.L, h.nT, jk) &&
+                  h.L <= LDS_MAX_L && group_items(h.L, h.nT) >= 64 &&
+                  group_lds_offsets(h.L, h.nT, jk).total <= lds_max;
+        if (h.hbm && !hbm_size(h.L))
+            return fail(EA_EUNSUPPORTED,
+                        "sample %d: L=%d with %d temperatures does not fit LDS (%zu of %zu B) and the HBM tier "
+                        "needs L in {8, 16, 24, 32}", s, h.L, h.nT, need, lds_max);
+        tot.any_hbm |= h.hbm;
+        if (h.hbm) tot.hbm_walkers += 2 * (int64_t)h.nT;
+        if (h.bits) {
+            h.jb_off = tot.jbits_words;
+            tot.jbits_words += 12 * (int64_t)(h.N / 64);
+        }
+        soff += 2 * (int64_t)h.nT * h.N;
+        joff += 3 * (int64_t)h.N;
+        foff += 2 * (int64_t)h.nT * h.L * h.L;
+        toff += h.nT;
+        smp.push_back(h);
+    }
+    tot.total_slots = toff;
+    tot.spin_bytes = soff;
+    tot.J_elems = joff;
+    tot.frame_words = foff;
+    return EA_OK;
+}
+
+// The persistent device buffers, in arena order (ea_bind_buffers), and their
+// sizes.  The snapshot frames (sized by the plan's chunk) and the scratch of
+// ea_check_energies stay outside.
+constexpr int NARENA = 25;
+constexpr size_t ARENA_ALIGN = 256;
+
+void arena_buffers(ea_ensemble *e, DevBuf *b[NARENA])
+{
+    DevBuf *list[NARENA] = {&e->samples, &e->items, &e->spins, &e->J, &e->beta, &e->beta32, &e->lut,
+                            &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->state,
+                            &e->slot_sample, &e->costab, &e->sintab, &e->finout, &e->dEJ, &e->dM,
+                            &e->sow, &e->walkers, &e->Ju, &e->mslots, &e->Jbits};
+    for (int k = 0; k < NARENA; ++k) b[k] = list[k];
+}
+
+void arena_sizes(int S, int jkind, const SampleTotals &t, size_t sz[NARENA])
+{
+    const size_t TS = (size_t)t.total_slots;
+    const size_t sizes[NARENA] = {
+        sizeof(SampleDev) * S, sizeof(int32_t) * 2 * S, (size_t)t.spin_bytes,
+        (size_t)t.J_elems * (jkind == EA_J_GAUSS_F32 ? 4 : 1), sizeof(double) * TS, sizeof(float) * TS,
+        sizeof(uint32_t) * 14 * TS, sizeof(int32_t) * 2 * TS, sizeof(int64_t) * 2 * TS,
+        sizeof(int32_t) * 2 * TS, sizeof(int64_t) * 2 * TS, sizeof(int64_t) * 2 * TS,
+        sizeof(double) * NACC * TS, 64, sizeof(int32_t) * TS, sizeof(double) * (MAX_L + 1) * MAX_L,
+        sizeof(double) * (MAX_L + 1) * MAX_L, sizeof(double) * 2 * MAX_T * EA_NOBS, sizeof(int64_t) * 2 * TS,
+        sizeof(int32_t) * 2 * TS, sizeof(int32_t) * 2 * TS, sizeof(int32_t) * (size_t)t.hbm_walkers,
+        t.any_hbm && jkind == EA_J_GAUSS_F32 ? sizeof(int32_t) * (size_t)t.J_elems : 0, sizeof(int32_t) * TS,
+        sizeof(uint32_t) * (size_t)t.jbits_words};
+    for (int k = 0; k < NARENA; ++k) sz[k] = sizes[k];
+}
+
+size_t arena_bytes(const size_t sz[NARENA])
+{
+    size_t total = 0;
+    for (int k = 0; k < NARENA; ++k) total += (sz[k] + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
+    return total;
+}
+
 ea_status run_sweeps(ea_ensemble *e, int64_t n, bool unbatched)
 {
     if (n < 0) return fail(EA_EINVAL, "n_sweeps must be >= 0");
@@ -647,48 +750,16 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         return fail(EA_EDEVICE, "no HIP device");
     }
     const size_t lds_max = max_lds_bytes();
-    int64_t soff = 0, joff = 0, foff = 0;
-    int32_t toff = 0;
-    for (int s = 0; s < e->S; ++s) {
-        SampleHost h{};
-        h.L = d->L[s];
-        h.nT = d->n_temps[s];
-        h.N = h.L * h.L * h.L;
-        h.id = d->sample_id ? d->sample_id[s] : (uint32_t)s;
-        h.h = d->h[s];
-        h.spin_off = soff;
-        h.J_off = joff;
-        h.slot_off = toff;
-        h.frame_off = foff;
-        const size_t need = lds_offsets(h.L, h.nT, e->jkind).total;
-        const bool fits = h.L <= LDS_MAX_L && need <= lds_max;
-        const bool forced_hbm = d->tier == EA_TIER_HBM && hbm_size(h.L);
-        h.bits = !forced_hbm && d->tier != EA_TIER_BYTES && d->tier != EA_TIER_SITE &&
-                 bits_engine(h.L, h.nT, e->jkind, h.h, lds_max);
-        h.hbm = !h.bits && (!fits || forced_hbm);
-        // the group engine needs a wave's worth of (quad, site group) items;
-        // tinier chains (L = 2, 4) keep the one-site-per-thread engine, which
-        // spreads them over more lanes
-        h.group = !h.hbm && !h.bits && d->tier != EA_TIER_SITE && !row_engine(h.L, h.nT, e->jkind) &&
-                  h.L <= LDS_MAX_L && group_items(h.L, h.nT) >= 64 &&
-                  group_lds_offsets(h.L, h.nT, e->jkind).total <= lds_max;
-        if (h.hbm && !hbm_size(h.L)) {
-            destroy_all(e);
-            return fail(EA_EUNSUPPORTED,
-                        "sample %d: L=%d with %d temperatures does not fit LDS (%zu of %zu B) and the HBM tier "
-                        "needs L in {8, 16, 24, 32}", s, h.L, h.nT, need, lds_max);
-        }
-        e->any_hbm |= h.hbm;
-        soff += 2 * (int64_t)h.nT * h.N;
-        joff += 3 * (int64_t)h.N;
-        foff += 2 * (int64_t)h.nT * h.L * h.L;
-        toff += h.nT;
-        e->smp.push_back(h);
+    SampleTotals tot;
+    if ((st = plan_samples(d, lds_max, e->smp, tot)) != EA_OK) {
+        destroy_all(e);
+        return st;
     }
-    e->total_slots = toff;
-    e->spin_bytes = soff;
-    e->J_elems = joff;
-    e->frame_words = foff;
+    e->any_hbm = tot.any_hbm;
+    e->total_slots = tot.total_slots;
+    e->spin_bytes = tot.spin_bytes;
+    e->J_elems = tot.J_elems;
+    e->frame_words = tot.frame_words;
 
     if (hip_stream) {
         e->stream = (hipStream_t)hip_stream;
@@ -868,40 +939,37 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         }
 
     const int64_t TS = e->total_slots;
-#define ALLOC(buf, bytes)                          \
-    do {                                           \
-        ea_status a_ = dalloc(e, e->buf, (bytes)); \
-        if (a_) {                                  \
-            destroy_all(e);                        \
-            return a_;                             \
-        }                                          \
+#define ALLOC_BUF(buf, bytes)                   \
+    do {                                        \
+        ea_status a_ = dalloc(e, (buf), (bytes)); \
+        if (a_) {                               \
+            destroy_all(e);                     \
+            return a_;                          \
+        }                                       \
     } while (0)
-    ALLOC(samples, sizeof(SampleDev) * S);
-    ALLOC(items, sizeof(int32_t) * 2 * S);
-    ALLOC(spins, (size_t)e->spin_bytes);
-    ALLOC(J, Jsub.size());
-    ALLOC(beta, sizeof(double) * TS);
-    ALLOC(beta32, sizeof(float) * TS);
-    ALLOC(lut, sizeof(uint32_t) * 14 * TS);
-    ALLOC(was, sizeof(int32_t) * 2 * TS);
-    ALLOC(EJ, sizeof(int64_t) * 2 * TS);
-    ALLOC(M, sizeof(int32_t) * 2 * TS);
-    ALLOC(flips, sizeof(int64_t) * 2 * TS);
-    ALLOC(swaps, sizeof(int64_t) * 2 * TS);
-    ALLOC(acc, sizeof(double) * NACC * TS);
-    ALLOC(state, 64);
-    ALLOC(slot_sample, sizeof(int32_t) * TS);
-    ALLOC(costab, sizeof(double) * costab.size());
-    ALLOC(sintab, sizeof(double) * sintab.size());
-    ALLOC(finout, sizeof(double) * 2 * MAX_T * EA_NOBS);
-    ALLOC(dEJ, sizeof(int64_t) * 2 * TS);
-    ALLOC(dM, sizeof(int32_t) * 2 * TS);
-    ALLOC(sow, sizeof(int32_t) * 2 * TS);
-    ALLOC(walkers, sizeof(int32_t) * wtab.size());
-    ALLOC(Ju, sizeof(int32_t) * Ju.size());
-    ALLOC(mslots, sizeof(int32_t) * mslots.size());
-    ALLOC(Jbits, sizeof(uint32_t) * Jbits.size());
-#undef ALLOC
+    {
+        // the persistent buffers (sizes shared with ea_query_sizes), checked
+        // against the host layouts just built
+        size_t sz[NARENA];
+        arena_sizes(S, e->jkind, tot, sz);
+        const size_t host_sz[NARENA] = {
+            sizeof(SampleDev) * S, sizeof(int32_t) * items.size(), spins.size(), Jsub.size(),
+            sizeof(double) * beta.size(), sizeof(float) * beta32.size(), sizeof(uint32_t) * lut.size(),
+            sizeof(int32_t) * was.size(), sz[8], sz[9], sz[10], sz[11], sz[12], sz[13],
+            sizeof(int32_t) * slot_sample.size(), sizeof(double) * costab.size(), sizeof(double) * sintab.size(),
+            sz[17], sz[18], sz[19], sz[20], sizeof(int32_t) * wtab.size(), sizeof(int32_t) * Ju.size(),
+            sizeof(int32_t) * mslots.size(), sizeof(uint32_t) * Jbits.size()};
+        DevBuf *bufs[NARENA];
+        arena_buffers(e, bufs);
+        for (int k = 0; k < NARENA; ++k) {
+            if (sz[k] != host_sz[k]) {
+                destroy_all(e);
+                return fail(EA_EDEVICE, "internal error: buffer %d size %zu, layout %zu", k, sz[k], host_sz[k]);
+            }
+            ALLOC_BUF(*bufs[k], sz[k]);
+        }
+    }
+#undef ALLOC_BUF
     {
         ea_status fs = ensure_frames(e, e->plan.chunk);
         if (fs) {
@@ -1269,6 +1337,69 @@ ea_status ea_synchronize(ea_ensemble *e)
 {
     if (!usable(e)) return EA_ESTATE;
     HIP_TRY(e, hipStreamSynchronize(e->stream));
+    return EA_OK;
+}
+
+ea_status ea_query_sizes(const ea_desc *d, size_t *device_bytes)
+{
+    if (!device_bytes) return fail(EA_EINVAL, "device_bytes is NULL");
+    *device_bytes = 0;
+    ea_status st = validate(d);
+    if (st) return st;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(EA_EDEVICE, "no HIP device");
+    std::vector<SampleHost> smp;
+    SampleTotals tot;
+    if ((st = plan_samples(d, max_lds_bytes(), smp, tot)) != EA_OK) return st;
+    size_t sz[NARENA];
+    arena_sizes(d->n_samples, d->jkind, tot, sz);
+    *device_bytes = arena_bytes(sz);
+    return EA_OK;
+}
+
+ea_status ea_bind_buffers(ea_ensemble *e, void *const *device_ptrs, size_t arena_bytes)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (!device_ptrs || !device_ptrs[0]) return fail(EA_EINVAL, "device_ptrs[0] is NULL");
+    if (e->bound) return fail(EA_ESTATE, "buffers are already bound");
+    char *base = (char *)device_ptrs[0];
+    if ((uintptr_t)base % ARENA_ALIGN) return fail(EA_EINVAL, "the arena must be %zu-byte aligned", ARENA_ALIGN);
+    DevBuf *bufs[NARENA];
+    arena_buffers(e, bufs);
+    size_t need = 0;
+    for (int k = 0; k < NARENA; ++k) need += (bufs[k]->bytes + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
+    if (arena_bytes < need) return fail(EA_EINVAL, "the arena needs %zu bytes, %zu given", need, arena_bytes);
+    // and the allocation holding it must reach its end
+    void *alloc_base = nullptr;
+    size_t alloc_size = 0;
+    if (hipMemGetAddressRange(&alloc_base, &alloc_size, base) != hipSuccess || !alloc_base)
+        return fail(EA_EINVAL, "device_ptrs[0] is not device memory of this process");
+    if ((size_t)(base - (char *)alloc_base) + need > alloc_size)
+        return fail(EA_EINVAL, "the arena needs %zu bytes, its allocation holds %zu past it", need,
+                    alloc_size - (size_t)(base - (char *)alloc_base));
+    // copy every buffer to its slice in stream order, wait, then switch over
+    size_t off[NARENA], pos = 0;
+    for (int k = 0; k < NARENA; ++k) {
+        off[k] = pos;
+        if (bufs[k]->bytes)
+            HIP_TRY(e, hipMemcpyAsync(base + pos, bufs[k]->p, bufs[k]->bytes, hipMemcpyDeviceToDevice, e->stream));
+        pos += (bufs[k]->bytes + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
+    }
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    for (int k = 0; k < NARENA; ++k) {
+        const size_t bytes = bufs[k]->bytes;
+        e->device_bytes -= (int64_t)bytes;
+        dfree(*bufs[k]);
+        bufs[k]->bytes = bytes;
+        bufs[k]->p = bytes ? base + off[k] : nullptr;
+        bufs[k]->owned = false;
+    }
+    // captured graphs hold the old addresses
+    for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : e->graph_defs) (void)hipGraphDestroy(kv.second);
+    e->graphs.clear();
+    e->graph_defs.clear();
+    e->bound = true;
     return EA_OK;
 }
 

@@ -248,7 +248,7 @@ __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleD
                                                const ItemLds &I, int w, int y, int k, int t, int &accE,
                                                int &nd, int &bf, int &bd)
 {
-    constexpr int N = L * L * L, WPR = L / 8, HL = L / 2;
+    constexpr int WPR = L / 8, HL = L / 2;
     const int yp = (y + 1) & (L - 1), ym = (y - 1) & (L - 1);
     const int kx = WPR == 2 ? (k ^ 1) : k;
     const int o_y0 = 4 * (y * WPR + k), o_yp = 4 * (yp * WPR + k), o_ym = 4 * (ym * WPR + k);

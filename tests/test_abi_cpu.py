@@ -133,3 +133,14 @@ def test_rejects_beta_beyond_the_acceptance_bound(small):
     d, keep = _desc(small, beta=b)
     st, h, msg = _create(d)
     assert st == -1 and not h.value and "2^20" in msg
+
+
+def test_query_sizes_and_bind_reject_null_arguments(small):
+    lib = binding.load()
+    n = ctypes.c_size_t(7)
+    assert lib.ea_query_sizes(None, ctypes.byref(n)) == -1
+    d, keep = _desc(small)
+    assert lib.ea_query_sizes(ctypes.byref(d), None) == -1
+    d, keep = _desc(small, L=np.array([4, 5], dtype=np.int32))
+    assert lib.ea_query_sizes(ctypes.byref(d), ctypes.byref(n)) == -5 and n.value == 0
+    assert lib.ea_bind_buffers(None, None, 0) == -4

@@ -106,6 +106,34 @@ def test_fields_and_temperatures_at_the_exponent_bounds(torch_cuda):
     check(work.subset([0, 1, 2, 3, 4, 7]), 24, tier=1)  # the HBM tier's half-sweep kernel
 
 
+def test_bind_buffers_to_caller_memory(torch_cuda):
+    # the persistent buffers moved into a torch tensor mid-run: same results
+    from paper_1403_4560_amd import binding
+    work = W.make_workload([8, 6, 16, 10], [4, 6, 3, 5], (0.5, 2.0), [0.2, 0.1, 0.3, 0.0], measure_every=4,
+                           measure_start=4, name="bound")
+    need = binding.query_sizes(work)
+    print("case: bind_buffers, arena %d bytes" % need, flush=True)
+    with binding.Ensemble(work) as ens:
+        before = ens.query()["device_bytes"]
+        ens.sweep_pt(12)
+        with pytest.raises(binding.EAError):
+            ens.bind_buffers(torch_cuda.empty(need // 2, dtype=torch_cuda.uint8, device="cuda"))
+        arena = torch_cuda.empty(need, dtype=torch_cuda.uint8, device="cuda")
+        ens.bind_buffers(arena)
+        moved = before - ens.query()["device_bytes"]
+        assert 0 < moved <= need < moved + 25 * 256
+        with pytest.raises(binding.EAError):
+            ens.bind_buffers(arena)
+        ens.sweep_pt(20)
+        st = ens.read_state()
+        ms = ens.measure()
+        bad = ens.check_energies()
+    ref = O.OracleEnsemble(work).run(32)
+    assert bad == 0
+    assert_same(work, st, ms, ref)
+    del arena
+
+
 def test_degenerate_sizes(torch_cuda):
     # L = 2 (every neighbour pair joined by two bonds), one temperature (no
     # exchange), an odd number of temperatures, L = 14
