@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="before timing, run a plain device-to-device copy of this many bytes "
                          "(a reference kernel of known traffic for hardware byte counters)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="print the measured rates of the roofline's units (VALU issue of xor, 64-bit "
+                         "multiply-add and high multiply; LDS read and HBM copy bandwidth) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: every disorder sample is independent, so more GPUs "
@@ -150,6 +153,14 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.peaks:
+        r = binding.measure_peaks()
+        print(json.dumps({"peaks_measured": {
+            "valu_xor_Tops": r["valu_xor_ops"] / 1e12, "valu_mad_u64_Tops": r["valu_mad_u64_ops"] / 1e12,
+            "valu_mul_hi_Tops": r["valu_mul_hi_ops"] / 1e12, "lds_read_TBps": r["lds_read_bytes"] / 1e12,
+            "hbm_copy_TBps": r["hbm_copy_bytes"] / 1e12},
+            "derived_valu_peak_Tops": VALU_PEAK_TOPS, "published_hbm_TBps": 8.0}))
+        return
     if args.copy_bytes > 0:
         src = torch.ones(args.copy_bytes, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

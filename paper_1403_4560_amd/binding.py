@@ -78,6 +78,7 @@ _SIGS = [
     ("ea_query_sizes", ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)]),
     ("ea_bind_buffers", ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_size_t]),
     ("ea_verify_exp_bracket", ctypes.c_int, [_VP, _VP]),
+    ("ea_measure_peaks", ctypes.c_int, [_VP]),
     ("ea_destroy", None, [_VP]),
     ("ea_last_error", ctypes.c_char_p, []),
 ]
@@ -101,6 +102,16 @@ def load():
 def _check(st):
     if st != 0:
         raise EAError(st, load().ea_last_error().decode(errors="replace"))
+
+
+PEAK_NAMES = ("valu_xor_ops", "valu_mad_u64_ops", "valu_mul_hi_ops", "lds_read_bytes", "hbm_copy_bytes")
+
+
+def measure_peaks() -> dict:
+    """Measured rates (per second) of the roofline's units on the current device."""
+    out = np.zeros(len(PEAK_NAMES), dtype=np.float64)
+    _check(load().ea_measure_peaks(_p(out)))
+    return dict(zip(PEAK_NAMES, out.tolist()))
 
 
 def verify_exp_bracket():

@@ -430,3 +430,13 @@ def test_engine_routing(torch_cuda):
         assert e.engines() == ["bits", "bits", "bits", "group", "hbm"]
     with binding.Ensemble(pm1.subset([0, 1, 2]), tier=2) as e:
         assert e.engines() == ["hbm", "group", "group"]
+
+
+def test_measure_peaks_runs(torch_cuda):
+    # the roofline's unit rates: positive and below what 256 CUs at 2.4 GHz can issue
+    from paper_1403_4560_amd import binding
+    r = binding.measure_peaks()
+    print("peaks:", {k: "%.3g" % v for k, v in r.items()}, flush=True)
+    for k in ("valu_xor_ops", "valu_mad_u64_ops", "valu_mul_hi_ops"):
+        assert 0 < r[k] < 1.1 * 256 * 64 * 2.5e9
+    assert 0 < r["lds_read_bytes"] and 0 < r["hbm_copy_bytes"] < 2e13
