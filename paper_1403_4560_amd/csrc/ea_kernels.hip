@@ -263,11 +263,15 @@ __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleD
     const float ka = cp * 0x1p-18f, kb = cp * (d.h32 - (float)d.hgrid * 0x1p-18f);
     float h32 = d.h32;  // exact path only
 #pragma unroll 1
-    for (int z = 0; z < L; z += 2) {
-        const int zm = z == 0 ? L - 1 : z - 1, zpp = z + 2 == L ? 0 : z + 2;
+    for (int z = 0; z < L; z += 4) {
+        const int zm = z == 0 ? L - 1 : z - 1, z4 = z + 4 == L ? 0 : z + 4;
         row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z, z + 1, zm, c1, c2, ka, kb, h32, accE,
                            nd, bf, bd);
-        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, zpp, z, c1, c2, ka, kb, h32,
+        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, z + 2, z, c1, c2, ka, kb, h32,
+                               accE, nd, bf, bd);
+        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 2, z + 3, z + 1, c1, c2, ka, kb, h32,
+                           accE, nd, bf, bd);
+        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 3, z4, z + 2, c1, c2, ka, kb, h32,
                                accE, nd, bf, bd);
     }
 }
