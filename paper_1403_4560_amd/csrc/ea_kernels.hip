@@ -193,11 +193,22 @@ struct RowMap {
     static constexpr int WPW = 64 / CPW;  // walkers per wave
 };
 
+// Row engine coupling layout in LDS: within each z plane the rows y are stored
+// in the order of row_slot (even y, then odd y), so the columns a wave holds
+// (one y parity) read one contiguous run of 16-byte coupling words.
+template <int L>
+__device__ __forceinline__ int row_slot(int y)
+{
+    return (y & 1) * (L / 2) + (y >> 1);
+}
+
+// j_y0, j_ym, je_prev: the coupling offsets of the word and of its -y neighbour
+// word, and the coupling element before the word, in that layout.
 template <int L, int P, int EPS>
 __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d, uint8_t *Sw, const int *J,
-                                         int o_y0, int o_yp, int o_ym, int o_x, int e_prev, int z, int zp,
-                                         int zm, uint32_t c1, uint32_t c2, float ka, float kb, float h32,
-                                         int &accE, int &nd, int &bf, int &bd)
+                                         int o_y0, int o_yp, int o_ym, int o_x, int j_y0, int j_ym, int je_prev,
+                                         int z, int zp, int zm, uint32_t c1, uint32_t c2, float ka, float kb,
+                                         float h32, int &accE, int &nd, int &bf, int &bd)
 {
     constexpr int HALF = L * L * L / 2, HL = L / 2, PLANE = L * HL;
     const uint8_t *own = Sw + P * HALF, *oth = Sw + (1 - P) * HALF;
@@ -211,19 +222,19 @@ __device__ __forceinline__ void row_word(const SweepArgs &A, const SampleDev &d,
     const uint32_t Zp = *(const uint32_t *)(oth + o_y0 + zp * PLANE);
     const uint32_t Zm = *(const uint32_t *)(oth + o_y0 + zm * PLANE);
     const uint32_t Xs = __builtin_amdgcn_perm(Xa, Xo, EPS ? 0x00070605u : 0x06050403u);
-    const int4 Jpx = *(const int4 *)(Jp + o_y0 + zo);
-    const int4 Jpy = *(const int4 *)(Jp + HALF + o_y0 + zo);
-    const int4 Jpz = *(const int4 *)(Jp + 2 * HALF + o_y0 + zo);
-    const int4 V = *(const int4 *)(Jo + o_y0 + zo);
-    const int4 Jym = *(const int4 *)(Jo + HALF + o_ym + zo);
-    const int4 Jzm = *(const int4 *)(Jo + 2 * HALF + o_y0 + zm * PLANE);
+    const int4 Jpx = *(const int4 *)(Jp + j_y0 + zo);
+    const int4 Jpy = *(const int4 *)(Jp + HALF + j_y0 + zo);
+    const int4 Jpz = *(const int4 *)(Jp + 2 * HALF + j_y0 + zo);
+    const int4 V = *(const int4 *)(Jo + j_y0 + zo);
+    const int4 Jym = *(const int4 *)(Jo + HALF + j_ym + zo);
+    const int4 Jzm = *(const int4 *)(Jo + 2 * HALF + j_y0 + zm * PLANE);
     // bonds to the aligned x-neighbour (x+1 if eps = 0, else x-1) and the shifted one
     int Ja[4], Js[4];
     if constexpr (EPS) {
         Ja[0] = V.x; Ja[1] = V.y; Ja[2] = V.z; Ja[3] = V.w;
         Js[0] = Jpx.x; Js[1] = Jpx.y; Js[2] = Jpx.z; Js[3] = Jpx.w;
     } else {
-        const int Ep = Jo[e_prev + zo];
+        const int Ep = Jo[je_prev + zo];
         Ja[0] = Jpx.x; Ja[1] = Jpx.y; Ja[2] = Jpx.z; Ja[3] = Jpx.w;
         Js[0] = Ep; Js[1] = V.x; Js[2] = V.y; Js[3] = V.z;
     }
@@ -253,7 +264,8 @@ __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleD
     const int kx = WPR == 2 ? (k ^ 1) : k;
     const int o_y0 = 4 * (y * WPR + k), o_yp = 4 * (yp * WPR + k), o_ym = 4 * (ym * WPR + k);
     const int o_x = 4 * (y * WPR + kx);
-    const int e_prev = y * HL + (k == 0 ? HL - 1 : 4 * k - 1);  // element before the word, cyclic
+    const int j_y0 = 4 * (row_slot<L>(y) * WPR + k), j_ym = 4 * (row_slot<L>(ym) * WPR + k);
+    const int je_prev = row_slot<L>(y) * HL + (k == 0 ? HL - 1 : 4 * k - 1);  // element before the word, cyclic
     uint8_t *Sw = (uint8_t *)I.S + (size_t)w * item_walker_stride(L);
     const int *J = (const int *)I.J;
     const uint32_t c1 = (uint32_t)(2 * n + P);
@@ -265,14 +277,14 @@ __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleD
 #pragma unroll 1
     for (int z = 0; z < L; z += 4) {
         const int zm = z == 0 ? L - 1 : z - 1, z4 = z + 4 == L ? 0 : z + 4;
-        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z, z + 1, zm, c1, c2, ka, kb, h32, accE,
-                           nd, bf, bd);
-        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 1, z + 2, z, c1, c2, ka, kb, h32,
-                               accE, nd, bf, bd);
-        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 2, z + 3, z + 1, c1, c2, ka, kb, h32,
-                           accE, nd, bf, bd);
-        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, e_prev, z + 3, z4, z + 2, c1, c2, ka, kb, h32,
-                               accE, nd, bf, bd);
+        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, j_y0, j_ym, je_prev, z, z + 1, zm, c1, c2, ka, kb,
+                           h32, accE, nd, bf, bd);
+        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, j_y0, j_ym, je_prev, z + 1, z + 2, z, c1, c2,
+                               ka, kb, h32, accE, nd, bf, bd);
+        row_word<L, P, E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, j_y0, j_ym, je_prev, z + 2, z + 3, z + 1, c1, c2,
+                           ka, kb, h32, accE, nd, bf, bd);
+        row_word<L, P, 1 - E0>(A, d, Sw, J, o_y0, o_yp, o_ym, o_x, j_y0, j_ym, je_prev, z + 3, z4, z + 2, c1, c2,
+                               ka, kb, h32, accE, nd, bf, bd);
     }
 }
 
@@ -306,13 +318,18 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
     const int gi = 2 * d.slot_off + r * nT;
     copy_walkers(I.S, item_walker_stride(L), A.spins + sbase, nT, N, true);
     if constexpr (ROW) {
-        // couplings as exact int32 multiples of 2^-18
+        // couplings as exact int32 multiples of 2^-18, rows of each z plane
+        // placed by row_slot (4 consecutive elements stay within one row)
+        constexpr int HALF = N / 2, HL = L / 2, PLANE = L * HL;
         const float4 *src = (const float4 *)((const float *)A.J + d.J_off);  // J_off is a multiple of 4
         int4 *dst = (int4 *)I.J;
         for (int i = tid; i < 3 * N / 4; i += T) {
             const float4 v = src[i];
-            dst[i] = make_int4((int)(v.x * 262144.0f), (int)(v.y * 262144.0f), (int)(v.z * 262144.0f),
-                               (int)(v.w * 262144.0f));
+            const int e = 4 * i, pd = e / HALF, h = e - pd * HALF;
+            const int row = h / HL, j = h - row * HL, y = row % L, z = row / L;
+            dst[(pd * HALF + z * PLANE + row_slot<L>(y) * HL + j) / 4] =
+                make_int4((int)(v.x * 262144.0f), (int)(v.y * 262144.0f), (int)(v.z * 262144.0f),
+                          (int)(v.w * 262144.0f));
         }
     } else {
         block_copy(I.J, (const char *)A.J + (size_t)d.J_off * (JK == 0 ? 4 : 1),

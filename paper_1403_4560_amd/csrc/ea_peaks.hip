@@ -155,26 +155,26 @@ extern "C" ea_status ea_measure_peaks(double *rates)
     const double valu_ops = lanes * rounds * PK_CHAINS;
     float ms = 0.f;
     hipError_t st = hipMemset(src, 0x5A, copy_bytes);
+    const dim3 grid(blocks), block(PK_THREADS);
     if (st == hipSuccess)
-        st = time_ms([&] { hipLaunchKernelGGL(peak_xor_kernel, dim3(blocks), dim3(PK_THREADS), 0, nullptr, out, 1u, rounds); },
-                     3, &ms);
+        st = time_ms([&] { hipLaunchKernelGGL(peak_xor_kernel, grid, block, 0, nullptr, out, 1u, rounds); }, 3, &ms);
     if (st == hipSuccess) rates[0] = valu_ops / (ms * 1e-3);
     if (st == hipSuccess)
-        st = time_ms([&] { hipLaunchKernelGGL(peak_mad64_kernel, dim3(blocks), dim3(PK_THREADS), 0, nullptr, out, 1u, rounds); },
-                     3, &ms);
+        st = time_ms([&] { hipLaunchKernelGGL(peak_mad64_kernel, grid, block, 0, nullptr, out, 1u, rounds); }, 3,
+                     &ms);
     if (st == hipSuccess) rates[1] = valu_ops / (ms * 1e-3);
     if (st == hipSuccess)
-        st = time_ms([&] { hipLaunchKernelGGL(peak_mulhi_kernel, dim3(blocks), dim3(PK_THREADS), 0, nullptr, out, 1u, rounds); },
-                     3, &ms);
+        st = time_ms([&] { hipLaunchKernelGGL(peak_mulhi_kernel, grid, block, 0, nullptr, out, 1u, rounds); }, 3,
+                     &ms);
     if (st == hipSuccess) rates[2] = valu_ops / (ms * 1e-3);
     const int lds_rounds = 4000;
     if (st == hipSuccess)
-        st = time_ms([&] { hipLaunchKernelGGL(peak_lds_kernel, dim3(blocks), dim3(PK_THREADS), 0, nullptr, out, 1u, lds_rounds); },
-                     3, &ms);
+        st = time_ms([&] { hipLaunchKernelGGL(peak_lds_kernel, grid, block, 0, nullptr, out, 1u, lds_rounds); }, 3,
+                     &ms);
     if (st == hipSuccess) rates[3] = lanes * lds_rounds * 8 * 16.0 / (ms * 1e-3);
     const size_t n16 = copy_bytes / 16;
     if (st == hipSuccess)
-        st = time_ms([&] { hipLaunchKernelGGL(peak_copy_kernel, dim3(cus * 32), dim3(PK_THREADS), 0, nullptr, dst, src, n16); },
+        st = time_ms([&] { hipLaunchKernelGGL(peak_copy_kernel, dim3(cus * 32), block, 0, nullptr, dst, src, n16); },
                      5, &ms);
     if (st == hipSuccess) rates[4] = 2.0 * (double)copy_bytes / (ms * 1e-3);
     (void)hipFree(out);
