@@ -288,6 +288,19 @@ def test_full_L16_workload_sampled(torch_cuda):
     assert_same(work, st, ms, ref, samples=pick)
 
 
+def test_L16_long_run_in_the_bench_plan(torch_cuda):
+    """Two L = 16 samples for 600 sweeps in the benchmark's plan (chunks of 100
+    replayed from a hipGraph), measuring every 10 sweeps from 300: spins,
+    walker maps, energies, counters and accumulators equal the oracle's."""
+    work = W.config_workload("L16_gauss", samples=[5, 1500], measure_start=300)
+    check(work, 600)
+
+
+def test_L32_pm1_longer_run(torch_cuda):
+    work = W.config_workload("L32_pm1", samples=[3], measure_start=20)
+    check(work, 60)
+
+
 def test_invalid_plan_rejected(torch_cuda):
     from paper_1403_4560_amd import binding
     work = W.make_workload([4], 2, (0.5, 2.0), 0.3)
