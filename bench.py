@@ -158,7 +158,7 @@ def main():
         print(json.dumps({"peaks_measured": {
             "valu_xor_Tops": r["valu_xor_ops"] / 1e12, "valu_mad_u64_Tops": r["valu_mad_u64_ops"] / 1e12,
             "valu_mul_hi_Tops": r["valu_mul_hi_ops"] / 1e12, "lds_read_TBps": r["lds_read_bytes"] / 1e12,
-            "hbm_copy_TBps": r["hbm_copy_bytes"] / 1e12},
+            "hbm_copy_TBps": r["hbm_copy_bytes"] / 1e12, "valu_exp_Tops": r["valu_exp_ops"] / 1e12},
             "derived_valu_peak_Tops": VALU_PEAK_TOPS, "published_hbm_TBps": 8.0}))
         return
     if args.copy_bytes > 0:

@@ -279,11 +279,12 @@ ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev);
 
 /* Microbenchmarks of the rates the kernels' rooflines are priced against, on
  * the current device (about a second; synchronizing; allocates and frees
- * 2 GiB for the copy).  rates_host[5] (caller-owned) receives, per second:
+ * 2 GiB for the copy).  rates_host[6] (caller-owned) receives, per second:
  * [0] v_xor_b32 lane-operations, [1] v_mad_u64_u32 lane-operations,
  * [2] v_mul_hi_u32 lane-operations (sixteen independent chains per lane, eight
  * waves per SIMD), [3] LDS bytes read (16-byte reads, no bank conflicts),
- * [4] HBM bytes read plus written by a 1 GiB device copy. */
+ * [4] HBM bytes read plus written by a 1 GiB device copy, [5] v_exp_f32
+ * lane-operations (as [0]). */
 ea_status ea_measure_peaks(double *rates_host);
 
 void ea_destroy(ea_ensemble *ens);

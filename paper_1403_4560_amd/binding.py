@@ -104,7 +104,8 @@ def _check(st):
         raise EAError(st, load().ea_last_error().decode(errors="replace"))
 
 
-PEAK_NAMES = ("valu_xor_ops", "valu_mad_u64_ops", "valu_mul_hi_ops", "lds_read_bytes", "hbm_copy_bytes")
+PEAK_NAMES = ("valu_xor_ops", "valu_mad_u64_ops", "valu_mul_hi_ops", "lds_read_bytes", "hbm_copy_bytes",
+              "valu_exp_ops")
 
 
 def measure_peaks() -> dict:

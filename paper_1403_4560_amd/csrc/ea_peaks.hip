@@ -2,7 +2,8 @@
 // are priced against: the issue rate of the three VALU instruction kinds the
 // Metropolis and Philox arithmetic is made of (a two-input xor stands for
 // the simple ops, the 32x32->64 multiply-add and the 32-bit high multiply for
-// the generator's products), LDS read bandwidth and HBM copy bandwidth.
+// the generator's products) and of the hardware exponential, LDS read
+// bandwidth and HBM copy bandwidth.
 //
 // Each VALU kernel runs 16 independent dependency chains per lane, so issue,
 // not latency, bounds it; the grid holds eight waves per SIMD.
@@ -69,6 +70,23 @@ __global__ void __launch_bounds__(PK_THREADS) peak_mulhi_kernel(uint32_t *out, u
 #pragma unroll
     for (int i = 0; i < PK_CHAINS; ++i) x ^= a[i];
     out[blockIdx.x * PK_THREADS + threadIdx.x] = x;
+}
+
+// v_exp_f32: a_i <- 2^(-a_i) stays in (0.5, 1) (the hardware exponential of
+// the acceptance estimate)
+__global__ void __launch_bounds__(PK_THREADS) peak_exp_kernel(uint32_t *out, uint32_t seed, int rounds)
+{
+    float a[PK_CHAINS];
+#pragma unroll
+    for (int i = 0; i < PK_CHAINS; ++i) a[i] = 0.5f + (float)((seed + i + threadIdx.x) & 255u) * 0x1p-9f;
+    for (int r = 0; r < rounds; ++r) {
+#pragma unroll
+        for (int i = 0; i < PK_CHAINS; ++i) asm volatile("v_exp_f32 %0, -%0" : "+v"(a[i]));
+    }
+    float x = 0.f;
+#pragma unroll
+    for (int i = 0; i < PK_CHAINS; ++i) x += a[i];
+    out[blockIdx.x * PK_THREADS + threadIdx.x] = __float_as_uint(x);
 }
 
 // LDS reads: 16 bytes per lane per read, consecutive lanes on consecutive
@@ -177,6 +195,9 @@ extern "C" ea_status ea_measure_peaks(double *rates)
         st = time_ms([&] { hipLaunchKernelGGL(peak_copy_kernel, dim3(cus * 32), block, 0, nullptr, dst, src, n16); },
                      5, &ms);
     if (st == hipSuccess) rates[4] = 2.0 * (double)copy_bytes / (ms * 1e-3);
+    if (st == hipSuccess)
+        st = time_ms([&] { hipLaunchKernelGGL(peak_exp_kernel, grid, block, 0, nullptr, out, 1u, rounds); }, 3, &ms);
+    if (st == hipSuccess) rates[5] = valu_ops / (ms * 1e-3);
     (void)hipFree(out);
     (void)hipFree(src);
     (void)hipFree(dst);

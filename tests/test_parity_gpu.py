@@ -451,6 +451,6 @@ def test_measure_peaks_runs(torch_cuda):
     from paper_1403_4560_amd import binding
     r = binding.measure_peaks()
     print("peaks:", {k: "%.3g" % v for k, v in r.items()}, flush=True)
-    for k in ("valu_xor_ops", "valu_mad_u64_ops", "valu_mul_hi_ops"):
+    for k in ("valu_xor_ops", "valu_mad_u64_ops", "valu_mul_hi_ops", "valu_exp_ops"):
         assert 0 < r[k] < 2 * 256 * 64 * 2.4e9
     assert 0 < r["lds_read_bytes"] and 0 < r["hbm_copy_bytes"] < 2e13
