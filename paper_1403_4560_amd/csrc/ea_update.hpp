@@ -45,8 +45,9 @@ __device__ __forceinline__ float flip_by_byte(float f, uint32_t m, int i)
 // is fl32(2 beta32 g) (the same real number, rounded once), dE <= 0 iff x >= 0,
 // exp_ea32 is 0 below -86.  The random word is decided by the sign of the gap
 // fl32(W - 2^(y + 32)) when its magnitude exceeds M (accept_gap), otherwise by
-// x >= 0 or U 2^-24 < exp_ea32(x), the contract's rule.  The exponent y
-// estimates x log2(e):
+// x >= 0 or U 2^-24 < exp_ea32(x), the contract's rule; one wave-uniform
+// branch per word takes that test for all four bytes in every lane as soon as
+// one byte of one lane needs it.  The exponent y estimates x log2(e):
 //   FOLD = false: y = fl32(c' g), ka[i] = c' = two_beta_log2e(beta32);
 //   FOLD = true:  y = -s_i fl32(fl32(S_u + hgrid) ka[i] + kb[i]) with
 //     ka[i] = c' 2^-18 and kb[i] = fl32(c' (h - hgrid 2^-18)), one fused
@@ -65,6 +66,7 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
     const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
     const uint32_t up = ~Sv & 0x80808080u;  // 0x80 in the bytes with s_i = +1
     uint32_t fm = 0;
+    uint64_t near = 0;  // lanes with some byte's gap within M of zero
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int sh = 8 * i;
@@ -76,32 +78,35 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
         Su += __mul24(__builtin_amdgcn_sbfe((int)Zm, sh, 8), Jzn[i]);
         if constexpr (FOLD) Su += hgrid;
         Sus[i] = Su;
-        float g, y;
+        float y;
         if constexpr (FOLD) {
             y = flip_by_byte(__builtin_fmaf((float)Su, ka[i], kb[i]), up, i);
         } else {
             // f = fl32(S_J + h): S_J = Su 2^-18 exactly, so the fused form rounds once, as the sum does
-            g = flip_by_byte(__builtin_fmaf((float)Su, 0x1p-18f, h32), up, i);  // -s_i f
-            y = ka[i] * g;
+            y = ka[i] * flip_by_byte(__builtin_fmaf((float)Su, 0x1p-18f, h32), up, i);  // c' (-s_i f)
         }
         const float gap = accept_gap(y, (float)words[i]);
-        const bool sure = gap < -ACCEPT_MARGIN, maybe = gap <= ACCEPT_MARGIN;  // sure implies maybe
-        bool accept = sure;
-        // If a lane of the wave has |gap| <= M (the two lane masks differ),
-        // every lane takes the exact test, which the gap only anticipates.
-        if (__builtin_amdgcn_ballot_w64(maybe) != __builtin_amdgcn_ballot_w64(sure)) {
-            if constexpr (FOLD) {
-                // S_u taken back from S_u + hgrid here only (the empty asm keeps
-                // the compiler from holding the sum without hgrid for this path,
-                // which would cost the main path a separate add)
-                int su = Su;
-                asm volatile("" : "+v"(su));
-                g = flip_by_byte(__builtin_fmaf((float)(su - hgrid), 0x1p-18f, h32), up, i);
-            }
-            const float x = b2_of(i) * g;  // = -fl32(beta dE)
-            accept = x >= 0.0f || (float)(words[i] >> 8) * 0x1p-24f < exp_ea32(x);
+        fm |= gap < -ACCEPT_MARGIN ? 0xFEu << sh : 0u;
+        near |= __builtin_amdgcn_ballot_w64(__builtin_fabsf(gap) <= ACCEPT_MARGIN);
+    }
+    // If any lane of the wave has a byte with |gap| <= M, every lane takes the
+    // exact test for all four bytes, which the gap only anticipates.  One
+    // wave-uniform branch per word lets the four bytes' chains interleave.
+    if (near != 0) {
+        fm = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            // S_u taken back from the stored sum here only (the empty asm keeps
+            // the compiler from holding the sum without hgrid for this path,
+            // which would cost the main path a separate add)
+            int su = Sus[i];
+            asm volatile("" : "+v"(su));
+            if constexpr (FOLD) su -= hgrid;
+            const float g = flip_by_byte(__builtin_fmaf((float)su, 0x1p-18f, h32), up, i);  // -s_i f
+            const float x = b2_of(i) * g;                                                  // = -fl32(beta dE)
+            const bool accept = x >= 0.0f || (float)(words[i] >> 8) * 0x1p-24f < exp_ea32(x);
+            fm |= accept ? 0xFEu << (8 * i) : 0u;
         }
-        fm |= accept ? 0xFEu << sh : 0u;
     }
     return fm;
 }
