@@ -299,7 +299,8 @@ __device__ __forceinline__ void run_bits_item(const SweepArgs &A, const SampleDe
     uint32_t *Sw = SB + (size_t)(on ? w : 0) * 2 * G;
     const double hd = (double)d.h32;
     const int64_t n0 = A.state[0];
-    const int64_t cnt0 = measurements_upto(n0, A.measure_every, A.measure_start);
+    int64_t next_meas = next_measurement(n0, A.measure_every, A.measure_start);
+    int64_t f = 0;  // frame of the next measurement within this chunk
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
         for (int i = tid; i < nT; i += T) I.sow[I.was[i]] = i;
@@ -333,9 +334,8 @@ __device__ __forceinline__ void run_bits_item(const SweepArgs &A, const SampleDe
         // Snapshot for the overlap measurement, in slot order: row (y, z) of
         // L bits interleaves the two sublattices' rows.
         const int64_t done = n + 1;
-        if (A.measure_every > 0 && done > A.measure_start &&
-            (done - A.measure_start) % A.measure_every == 0) {
-            const int64_t f = measurements_upto(done, A.measure_every, A.measure_start) - cnt0 - 1;
+        if (done == next_meas) {
+            next_meas += A.measure_every;
             uint32_t *dst = A.frames + f * A.frame_words + d.frame_off + (size_t)r * nT * L * L;
             for (int i = tid; i < nT * L * L; i += T) {
                 const int ts = i / (L * L), row = i - ts * (L * L);
@@ -351,6 +351,7 @@ __device__ __forceinline__ void run_bits_item(const SweepArgs &A, const SampleDe
                 const int ww = I.was[ts];
                 A.frameE[f * 2 * A.total_slots + gi + ts] = (double)I.EJ[ww] - hd * (double)I.M[ww];
             }
+            ++f;
         }
     }
     __syncthreads();

@@ -225,7 +225,8 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     const double unit = JK == 0 ? 0x1p-18 : 1.0;
     const double hd = (double)d.h32;
     const int64_t n0 = A.state[0];
-    const int64_t cnt0 = measurements_upto(n0, A.measure_every, A.measure_start);
+    int64_t next_meas = next_measurement(n0, A.measure_every, A.measure_start);
+    int64_t f = 0;  // frame of the next measurement within this chunk
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
         for (int i = tid; i < nT; i += T) {
@@ -280,9 +281,8 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         __syncthreads();
         // Snapshot for the overlap measurement, in slot order.
         const int64_t done = n + 1;
-        if (A.measure_every > 0 && done > A.measure_start &&
-            (done - A.measure_start) % A.measure_every == 0) {
-            const int64_t f = measurements_upto(done, A.measure_every, A.measure_start) - cnt0 - 1;
+        if (done == next_meas) {
+            next_meas += A.measure_every;
             uint32_t *dst = A.frames + f * A.frame_words + d.frame_off + (size_t)r * nT * L * L;
             for (int i = tid; i < nT * L * L; i += T) {
                 const int t = i / (L * L), row = i - t * (L * L);
@@ -299,6 +299,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
                 const int w = I.was[t];
                 A.frameE[f * 2 * A.total_slots + gi + t] = (double)I.EJ[w] * unit - hd * (double)I.M[w];
             }
+            ++f;
         }
     }
     __syncthreads();

@@ -293,13 +293,33 @@ __device__ __forceinline__ void row_half_sweep(const SweepArgs &A, const SampleD
 template <int L>
 __device__ __forceinline__ uint32_t pack_row_lds(const int8_t *Sw, int row)
 {
-    constexpr int HALF = L * L * L / 2;
+    constexpr int HALF = L * L * L / 2, HL = L / 2;
     const int yz = (row % L) + row / L;
     uint32_t bits = 0;
+    if constexpr (L % 8 == 0) {
+        // The row's HL bytes in each half are its sites in x order, the even x
+        // in half (yz & 1), the odd x in the other.  Per 8 sites: two byte
+        // permutes interleave them (x = 8g .. 8g+3 and 8g+4 .. 8g+7), the sign
+        // bits go to bits 3 and 7 of each byte, and one multiply by
+        // 2^21 + 2^14 + 2^7 + 1 carries the sign of x = 8g + k to bit 24 + k
+        // (the other partial products fall on distinct bits below 24 or
+        // beyond 31, so nothing carries into the result).
+        const uint32_t *h0 = (const uint32_t *)(Sw + row * HL), *h1 = (const uint32_t *)(Sw + HALF + row * HL);
+        const uint32_t flip = (yz & 1) ? 0x04040404u : 0u;
+        const uint32_t sel_lo = 0x05010400u ^ flip, sel_hi = 0x07030602u ^ flip;
 #pragma unroll
-    for (int x = 0; x < L; ++x) {
-        const int p = (x + yz) & 1;
-        bits |= (uint32_t)(Sw[p * HALF + ((x + L * row) >> 1)] < 0) << x;
+        for (int g = 0; g < L / 8; ++g) {
+            const uint32_t a = h0[g], b = h1[g];
+            const uint32_t lo = __builtin_amdgcn_perm(b, a, sel_lo), hi = __builtin_amdgcn_perm(b, a, sel_hi);
+            const uint32_t m = ((lo & 0x80808080u) >> 4) | (hi & 0x80808080u);
+            bits |= ((m * 0x00204081u) >> 24) << (8 * g);
+        }
+    } else {
+#pragma unroll
+        for (int x = 0; x < L; ++x) {
+            const int p = (x + yz) & 1;
+            bits |= (uint32_t)(Sw[p * HALF + ((x + L * row) >> 1)] < 0) << x;
+        }
     }
     return bits;
 }
@@ -360,7 +380,8 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
     const double unit = JK == 0 ? 0x1p-18 : 1.0;
     const double hd = (double)d.h32;
     const int64_t n0 = A.state[0];
-    const int64_t cnt0 = measurements_upto(n0, A.measure_every, A.measure_start);
+    int64_t next_meas = next_measurement(n0, A.measure_every, A.measure_start);
+    int64_t f = 0;  // frame of the next measurement within this chunk
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
         for (int i = tid; i < nT; i += T) {
@@ -413,9 +434,8 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
         __syncthreads();
         // Snapshot for the overlap measurement, in slot order.
         const int64_t done = n + 1;
-        if (A.measure_every > 0 && done > A.measure_start &&
-            (done - A.measure_start) % A.measure_every == 0) {
-            const int64_t f = measurements_upto(done, A.measure_every, A.measure_start) - cnt0 - 1;
+        if (done == next_meas) {
+            next_meas += A.measure_every;
             uint32_t *dst = A.frames + f * A.frame_words + d.frame_off + (size_t)r * nT * L * L;
             for (int i = tid; i < nT * L * L; i += T) {
                 const int t = i / (L * L), row = i - t * (L * L);
@@ -425,6 +445,7 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
                 const int w = I.was[t];
                 A.frameE[f * 2 * A.total_slots + gi + t] = (double)I.EJ[w] * unit - hd * (double)I.M[w];
             }
+            ++f;
         }
     }
     __syncthreads();

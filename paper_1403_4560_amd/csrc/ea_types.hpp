@@ -116,6 +116,15 @@ __host__ __device__ inline int64_t measurements_upto(int64_t x, int32_t m, int64
     return (x - start) / m;
 }
 
+// The first completed-sweep count beyond x at which a measurement is taken:
+// the least start + k m > x with k >= 1 (INT64_MAX if m <= 0).  Sweep loops
+// step it by m instead of testing every count with a 64-bit division.
+__host__ __device__ inline int64_t next_measurement(int64_t x, int32_t m, int64_t start)
+{
+    if (m <= 0) return INT64_MAX;
+    return start + (measurements_upto(x, m, start) + 1) * m;
+}
+
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // LDS layout of one LDS-tier work item (bytes).  Shared with the host, which
