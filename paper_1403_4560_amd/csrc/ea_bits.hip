@@ -280,6 +280,7 @@ __device__ __forceinline__ void run_bits_item(const SweepArgs &A, const SampleDe
     }
     for (int i = tid; i < nT; i += T) {
         I.was[i] = A.was[gi + i];
+        I.sow[A.was[gi + i]] = i;  // kept by exchange_pass from here on
         I.EJ[i] = A.EJ[gi + i];
         I.M[i] = A.M[gi + i];
         I.fl[i] = 0;
@@ -303,8 +304,6 @@ __device__ __forceinline__ void run_bits_item(const SweepArgs &A, const SampleDe
     int64_t f = 0;  // frame of the next measurement within this chunk
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
-        for (int i = tid; i < nT; i += T) I.sow[I.was[i]] = i;
-        __syncthreads();
         const int t = on ? I.sow[w] : 0;
         const uint32_t th_base = lds_addr(smem + TH_OFF + 32 * t);
         const uint32_t c2 = (PURPOSE_METROPOLIS << 28) | ((uint32_t)t << 1) | (uint32_t)r;
@@ -352,6 +351,7 @@ __device__ __forceinline__ void run_bits_item(const SweepArgs &A, const SampleDe
                 A.frameE[f * 2 * A.total_slots + gi + ts] = (double)I.EJ[ww] - hd * (double)I.M[ww];
             }
             ++f;
+            __syncthreads();  // the next sweep changes the spins read here
         }
     }
     __syncthreads();

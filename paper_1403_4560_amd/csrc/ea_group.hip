@@ -207,6 +207,9 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     }
     for (int i = tid; i < nT; i += T) {
         I.was[i] = A.was[gi + i];
+        I.sow[A.was[gi + i]] = i;  // kept by exchange_pass from here on
+        I.dEJ[i] = 0;
+        I.dM[i] = 0;
         I.EJ[i] = A.EJ[gi + i];
         I.M[i] = A.M[gi + i];
         I.fl[i] = 0;
@@ -229,12 +232,6 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     int64_t f = 0;  // frame of the next measurement within this chunk
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
-        for (int i = tid; i < nT; i += T) {
-            I.sow[I.was[i]] = i;
-            I.dEJ[i] = 0;
-            I.dM[i] = 0;
-        }
-        __syncthreads();
         GroupLane ln;
         int ts[4];
         for (int i = 0; i < 4; ++i) {
@@ -275,6 +272,8 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         for (int i = tid; i < nT; i += T) {
             I.EJ[i] = -I.dEJ[i];
             I.M[i] += I.dM[i];
+            I.dEJ[i] = 0;  // cleared for the next sweep's tallies
+            I.dM[i] = 0;
         }
         __syncthreads();
         exchange_pass(A, d, r, n, I, unit, hd);
@@ -300,6 +299,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
                 A.frameE[f * 2 * A.total_slots + gi + t] = (double)I.EJ[w] * unit - hd * (double)I.M[w];
             }
             ++f;
+            __syncthreads();  // the next sweep changes the spins read here
         }
     }
     __syncthreads();

@@ -139,7 +139,9 @@ __device__ __forceinline__ ItemLds item_lds(char *smem, int L, int nT, int jkind
 // (Methods: parallel tempering; even-odd pairs alternate with the sweep
 // parity).  D = (beta_t - beta_{t+1}) (E_t - E_{t+1}) in binary64; accepted
 // iff D >= 0 or u53 < exp_ea64(D), the uniform from the exchange counter
-// (0, n, (1 << 28) | (t << 1) | r, sample).  Swaps walker labels only.
+// (0, n, (1 << 28) | (t << 1) | r, sample).  Swaps walker labels only, in
+// both maps (was: slot -> walker, sow: walker -> slot), so the sweep that
+// follows reads its temperatures without rebuilding sow.
 __device__ __forceinline__ void exchange_pass(const SweepArgs &A, const SampleDev &d, int r, int64_t n,
                                               const ItemLds &I, double unit, double hd)
 {
@@ -161,6 +163,8 @@ __device__ __forceinline__ void exchange_pass(const SweepArgs &A, const SampleDe
         if (acc) {
             I.was[t] = w1;
             I.was[t + 1] = w0;
+            I.sow[w1] = t;
+            I.sow[w0] = t + 1;
             I.sw[t] += 1;
         }
     }
