@@ -66,7 +66,7 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
     const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
     const uint32_t up = ~Sv & 0x80808080u;  // 0x80 in the bytes with s_i = +1
     uint32_t fm = 0;
-    uint64_t near = 0;  // lanes with some byte's gap within M of zero
+    float gmin = __builtin_inff();  // the least |gap| of the four bytes
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int sh = 8 * i;
@@ -87,12 +87,12 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
         }
         const float gap = accept_gap(y, (float)words[i]);
         fm |= gap < -ACCEPT_MARGIN ? 0xFEu << sh : 0u;
-        near |= __builtin_amdgcn_ballot_w64(__builtin_fabsf(gap) <= ACCEPT_MARGIN);
+        gmin = __builtin_fminf(gmin, __builtin_fabsf(gap));
     }
     // If any lane of the wave has a byte with |gap| <= M, every lane takes the
     // exact test for all four bytes, which the gap only anticipates.  One
     // wave-uniform branch per word lets the four bytes' chains interleave.
-    if (near != 0) {
+    if (__builtin_amdgcn_ballot_w64(gmin <= ACCEPT_MARGIN) != 0) {
         fm = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
