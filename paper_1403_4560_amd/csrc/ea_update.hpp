@@ -65,7 +65,7 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
 {
     const uint32_t words[4] = {rw.x, rw.y, rw.z, rw.w};
     const uint32_t up = ~Sv & 0x80808080u;  // 0x80 in the bytes with s_i = +1
-    uint32_t fm = 0;
+    float gap[4];
     float gmin = __builtin_inff();  // the least |gap| of the four bytes
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -85,10 +85,15 @@ __device__ __forceinline__ uint32_t update_word_gauss(uint32_t Sv, uint32_t Xa, 
             // f = fl32(S_J + h): S_J = Su 2^-18 exactly, so the fused form rounds once, as the sum does
             y = ka[i] * flip_by_byte(__builtin_fmaf((float)Su, 0x1p-18f, h32), up, i);  // c' (-s_i f)
         }
-        const float gap = accept_gap(y, (float)words[i]);
-        fm |= gap < -ACCEPT_MARGIN ? 0xFEu << sh : 0u;
-        gmin = __builtin_fminf(gmin, __builtin_fabsf(gap));
+        gap[i] = accept_gap(y, (float)words[i]);
+        gmin = __builtin_fminf(gmin, __builtin_fabsf(gap[i]));
     }
+    // With every |gap| above M a byte is accepted iff its gap is negative:
+    // byte permutes with selectors 9 and 11 replicate the sign bit of the low
+    // and high source word into a whole byte.
+    uint32_t fm = (__builtin_amdgcn_perm(__float_as_uint(gap[1]), __float_as_uint(gap[0]), 0x0C0C0B09u) |
+                   __builtin_amdgcn_perm(__float_as_uint(gap[3]), __float_as_uint(gap[2]), 0x0B090C0Cu)) &
+                  0xFEFEFEFEu;
     // If any lane of the wave has a byte with |gap| <= M, every lane takes the
     // exact test for all four bytes, which the gap only anticipates.  One
     // wave-uniform branch per word lets the four bytes' chains interleave.
