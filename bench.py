@@ -56,14 +56,15 @@ WORKLOAD_TEXT = {
 #   per site, Gaussian couplings: 6 byte-select multiplies and 3 adds for
 #     S_u plus the field's grid part, conversion (1), one fused operation for
 #     the temperature and the field remainder (1), the spin's sign (1),
-#     hardware exponential (1), word to float (1), the acceptance gap (1),
-#     two compares (2), flip byte (1)                          = 19 x 4 = 76
+#     hardware exponential (1), word to float (1), the acceptance gap (1)
+#                                                              = 15 x 4 = 60
 #   the word's spin-sign mask (1)                                      =  1
-#   word tail: flip-mask merge (2), new spins (1), flip and down-flip
-#     counts (3)                                                      =  6
+#   flip mask from the gaps' sign bits: 2 byte permutes and 1 and       =  3
+#   exact-path test: least |gap| by 2 three-way minimums, 1 compare     =  3
+#   word tail: new spins (1), flip and down-flip counts (3)            =  4
 #   energy, second half-sweep only: per site sign-extend and xor (2), two
 #     adds per word, down count (2): 12 per word, 6 on average        =  6
-# Gaussian: (37 + 1 + 76 + 1 + 6 + 6) / 4 = 31.75.
+# Gaussian: (37 + 1 + 60 + 1 + 3 + 3 + 4 + 6) / 4 = 28.75.
 # +-1 couplings, one bit per spin, per 32-site word / 32:
 #   Philox 8 x 37 = 296; per site: table address (1), compare and carry-in
 #   (2) = 96; class bytes: 3 spread-table addresses (2 each) and 4 merges per
@@ -72,7 +73,7 @@ WORKLOAD_TEXT = {
 #   (3), new spins (1), flip and down-flip counts (3), energy on the second
 #   half only (7, 3.5 on average) = 42.5: 474.5 / 32 = 14.83.
 BYTE_PM1_OPS_PER_ATTEMPT = 25.5
-ALG_OPS_PER_ATTEMPT = {"L16_gauss": 31.75, "L8_gauss": 31.75, "mixed_L6_12": 31.75, "L4_gauss": 31.75,
+ALG_OPS_PER_ATTEMPT = {"L16_gauss": 28.75, "L8_gauss": 28.75, "mixed_L6_12": 28.75, "L4_gauss": 28.75,
                        "L32_pm1": 474.5 / 32}
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = non-packed VALU lane-instructions/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -81,7 +82,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the factors a plain copy of
 # known size reads), keyed by a fingerprint of the kernel sources they were
 # taken on; reported as null once the kernels change.
-MEASURED_TRAFFIC = {"L16_gauss": ("4d5101a6e217cd2e", 2.4352e9), "L32_pm1": ("4d5101a6e217cd2e", 3.5382e9)}
+MEASURED_TRAFFIC = {"L16_gauss": ("b11a8e83f689c066", 2.2589e9), "L32_pm1": ("b11a8e83f689c066", 3.5384e9)}
 KERNEL_SOURCES = tuple("paper_1403_4560_amd/csrc/" + f for f in (
     "ea_kernels.hip", "ea_bits.hip", "ea_group.hip", "ea_item.hpp", "ea_update.hpp", "ea_device.hpp",
     "ea_types.hpp"))
