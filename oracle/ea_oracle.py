@@ -231,6 +231,76 @@ class OracleEnsemble:
 
 # --------------------------------------------------------------------------
 # finalize: disorder averages (overline) of thermal averages (<...>), eqs. 3-6
+#
+# Reading of the disorder average (the paper's overline, an average over
+# disorder realizations of one model at one field and ladder): the exact sum
+# of the S per-sample values, rounded once to binary64 (nearest, ties to even),
+# then divided by S in one rounded division.  A leave-one-sample-out replicate
+# (jackknife) is the exact sum of the other S - 1 values rounded once, divided
+# by S - 1.  Exact sums are integer sums in units of 2^-1074 (every finite
+# binary64 is an integer multiple of that unit), so no result depends on the
+# order of the samples.  Non-finite values follow IEEE addition: any NaN, or
+# +inf together with -inf, gives NaN; otherwise an infinity wins.
+_UNIT_EXP = 1074
+
+
+def _as_units(x: float) -> int:
+    """Finite binary64 x as the exact integer x * 2^1074."""
+    n, d = float(x).as_integer_ratio()
+    return n << (_UNIT_EXP - (d.bit_length() - 1))
+
+
+def _from_units(v: int) -> float:
+    """v * 2^-1074 rounded once to binary64 (int true division is correctly
+    rounded)."""
+    try:
+        return v / (1 << _UNIT_EXP)
+    except OverflowError:
+        return math.copysign(math.inf, v)
+
+
+class ExactColumn:
+    """The exact sum of a multiset of binary64 values (one column: one slot
+    and one accumulator, over samples)."""
+
+    def __init__(self, values):
+        v = np.asarray(values, dtype=np.float64)
+        fin = np.isfinite(v)
+        self.n_nan = int(np.isnan(v).sum())
+        self.n_pinf = int((v == np.inf).sum())
+        self.n_ninf = int((v == -np.inf).sum())
+        self.units = [(_as_units(x) if ok else 0) for x, ok in zip(v.tolist(), fin.tolist())]
+        self.total = sum(self.units)
+        self.values = v
+
+    def _special(self, n_nan, n_pinf, n_ninf):
+        if n_nan or (n_pinf and n_ninf):
+            return math.nan
+        if n_pinf:
+            return math.inf
+        if n_ninf:
+            return -math.inf
+        return None
+
+    def rounded(self) -> float:
+        """The correctly rounded sum of every value."""
+        sp = self._special(self.n_nan, self.n_pinf, self.n_ninf)
+        return sp if sp is not None else _from_units(self.total)
+
+    def rounded_without(self, s: int) -> float:
+        """The correctly rounded sum of every value but the s-th."""
+        x = float(self.values[s])
+        sp = self._special(self.n_nan - math.isnan(x), self.n_pinf - (x == math.inf),
+                           self.n_ninf - (x == -math.inf))
+        return sp if sp is not None else _from_units(self.total - self.units[s])
+
+
+def exact_sum(values) -> float:
+    """Correctly rounded sum of binary64 values (equals math.fsum on finite
+    input)."""
+    return ExactColumn(values).rounded()
+
+
 def thermal_means(acc: np.ndarray) -> np.ndarray:
     """Per-sample thermal averages <.> = accumulated sum / number of
     measurements; acc has shape [S][n_T][36]."""
@@ -239,59 +309,90 @@ def thermal_means(acc: np.ndarray) -> np.ndarray:
         return acc / n
 
 
-def observables(acc: np.ndarray, L: int) -> dict:
-    """Disorder-averaged observables per temperature slot from the
-    accumulators of S samples of one lattice size ([S][n_T][36]).
+OBS_NAMES = ("q", "chi0", "chi_kmin", "chi_k2", "g", "xi_L", "R12", "chi0_over_chikmin", "E_a", "E_b")
 
-    chi(k) = N([<|q(k)|^2>] - |[<q(k)>]|^2)                         eq. 4
-    chi(k_min): mean over the three axis directions            Results
-    g = (3 - [<(q-Q)^4>] / [<(q-Q)^2>]^2) / 2, Q = [<q(0)>]            eq. 3
-    xi_L = sqrt(chi(0)/chi(k_min) - 1) / (2 sin(pi/L))                 eq. 5
-    R12 = chi(k1) / chi(k2), k2 = (2pi/L,2pi/L,0) and its images       eq. 6
+
+def observables_of_means(D: np.ndarray, L: int) -> dict:
+    """Observables per temperature slot from disorder-averaged thermal means
+    D [n_T][36] (column layout of the accumulators), each formula evaluated
+    in the order written (binary64, one rounding per operation):
+
+    chi(k) = N([<|q(k)|^2>] - |[<q(k)>]|^2)                          eq. 4
+    chi(k_min) = (chi_x + chi_y + chi_z) / 3                     Results
+    chi(k2) = mean of the six (1,1,0) images, summed in image order
+    g = (3 - [<(q-Q)^4>] / [<(q-Q)^2>]^2) / 2, Q = [<q(0)>], the central
+        moments expanded in raw moments                               eq. 3
+    xi_L = sqrt(chi(0)/chi(k_min) - 1) / (2 sin(pi/L))                eq. 5
+    R12 = chi(k_min) / chi(k2)                                        eq. 6
     """
-    N = float(L) ** 3
-    m = thermal_means(acc)                       # [S][n_T][36]
-    D = m.mean(axis=0)                           # disorder average
+    N = float(L * L * L)
+    D = np.asarray(D, dtype=np.float64)
     q1, q2, q3, q4 = D[:, 1], D[:, 2], D[:, 3], D[:, 4]
     Q = q1
-    # central moments about the disorder-averaged <q>, expanded in raw moments
     c2 = q2 - 2.0 * Q * q1 + Q * Q
-    c4 = q4 - 4.0 * Q * q3 + 6.0 * Q * Q * q2 - 4.0 * Q ** 3 * q1 + Q ** 4
-    g = 0.5 * (3.0 - c4 / (c2 * c2))
-    chi0 = N * (q2 - q1 * q1)
-
-    def chi_family(f):
+    c4 = q4 - 4.0 * Q * q3 + 6.0 * Q * Q * q2 - 4.0 * Q * Q * Q * q1 + Q * Q * Q * Q
+    chi = []
+    for f in range(NPLANE):
         re, im, k2 = D[:, 5 + 3 * f], D[:, 6 + 3 * f], D[:, 7 + 3 * f]
-        return N * (k2 - (re * re + im * im))
-
-    chi_axes = np.stack([chi_family(f) for f in range(3)])
-    chi_kmin = chi_axes.mean(axis=0)
-    chi_diag = np.stack([chi_family(f) for f in range(3, 9)])
-    chi_k2 = chi_diag.mean(axis=0)
+        chi.append(N * (k2 - (re * re + im * im)))
+    chi0 = N * (q2 - q1 * q1)
+    chi_kmin = (chi[0] + chi[1] + chi[2]) / 3.0
+    chi_k2 = (chi[3] + chi[4] + chi[5] + chi[6] + chi[7] + chi[8]) / 6.0
     with np.errstate(invalid="ignore", divide="ignore"):
+        g = 0.5 * (3.0 - c4 / (c2 * c2))
         xi = np.sqrt(chi0 / chi_kmin - 1.0) / (2.0 * math.sin(math.pi / L))
         r12 = chi_kmin / chi_k2
         ratio = chi0 / chi_kmin
-    return {"chi0": chi0, "chi_kmin": chi_kmin, "chi_k2": chi_k2, "g": g,
-            "xi_L": xi, "xi_over_L": xi / L, "R12": r12, "chi0_over_chikmin": ratio,
-            "q": q1, "E_a": D[:, 32], "E_b": D[:, 34]}
+    return {"q": q1, "chi0": chi0, "chi_kmin": chi_kmin, "chi_k2": chi_k2, "g": g, "xi_L": xi,
+            "R12": r12, "chi0_over_chikmin": ratio, "E_a": D[:, 32], "E_b": D[:, 34]}
+
+
+def _columns(m: np.ndarray):
+    """ExactColumn per (slot, accumulator) of per-sample values m [S][n_T][K]."""
+    return [[ExactColumn(m[:, t, j]) for j in range(m.shape[2])] for t in range(m.shape[1])]
+
+
+def disorder_means(acc: np.ndarray) -> np.ndarray:
+    """[n_T][36] disorder averages of the thermal means of S samples of one
+    system (the reading above)."""
+    m = thermal_means(np.asarray(acc, dtype=np.float64))
+    S = m.shape[0]
+    cols = _columns(m)
+    return np.array([[c.rounded() / S for c in row] for row in cols])
+
+
+def observables(acc: np.ndarray, L: int) -> dict:
+    """Disorder-averaged observables per temperature slot from the
+    accumulators of S samples of one system ([S][n_T][36])."""
+    out = observables_of_means(disorder_means(acc), L)
+    out["xi_over_L"] = out["xi_L"] / L
+    return out
 
 
 def jackknife(acc: np.ndarray, L: int) -> dict:
     """Leave-one-sample-out jackknife errors of every observable (Methods,
-    last paragraph: statistical errors from disorder averaging)."""
-    S = acc.shape[0]
+    last paragraph: statistical errors from disorder averaging).  Replicate
+    s: observables of the means of the other S - 1 samples; mean of the
+    replicates theta_bar = (exact sum)/S; error sqrt(((S-1)/S) sum_s
+    (theta_s - theta_bar)^2) with the sum exact and rounded once."""
+    m = thermal_means(np.asarray(acc, dtype=np.float64))
+    S, nT = m.shape[0], m.shape[1]
     full = observables(acc, L)
     if S < 2:
         return {k: (v, np.full_like(v, np.nan)) for k, v in full.items()}
-    reps = {k: [] for k in full}
+    cols = _columns(m)
+    reps = []
     for s in range(S):
-        o = observables(np.delete(acc, s, axis=0), L)
-        for k in full:
-            reps[k].append(o[k])
+        Ds = np.array([[c.rounded_without(s) / (S - 1) for c in row] for row in cols])
+        reps.append(observables_of_means(Ds, L))
     out = {}
-    for k, v in full.items():
-        R = np.stack(reps[k])
-        err = np.sqrt((S - 1) / S * ((R - R.mean(axis=0)) ** 2).sum(axis=0))
-        out[k] = (v, err)
+    for k in OBS_NAMES:
+        R = np.stack([r[k] for r in reps])                  # [S][n_T]
+        err = np.empty(nT)
+        for t in range(nT):
+            bar = exact_sum(R[:, t]) / S
+            d = R[:, t] - bar
+            err[t] = math.sqrt((S - 1) / S * exact_sum(d * d))
+        out[k] = (full[k], err)
+    out["xi_over_L"] = (full["xi_over_L"], out["xi_L"][1] / L)
     return out

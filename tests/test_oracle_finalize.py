@@ -100,3 +100,75 @@ def test_jackknife_of_mean_is_standard_error():
     per = acc[..., 1] / 10.0
     assert np.allclose(val, per.mean(axis=0), rtol=1e-14)
     assert np.allclose(err, per.std(axis=0, ddof=1) / math.sqrt(S), rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# The disorder average is read as the exact sum rounded once (then one
+# rounded division by the count).  Pinned against math.fsum (a correctly
+# rounded library sum) and exact rationals, on inputs chosen to defeat
+# ordinary summation: cancellation, exponents far apart, subnormals.
+def adversarial_arrays():
+    rng = np.random.default_rng(7)
+    yield np.array([1e16, 1.0, -1e16, 1e-16, 3.0])
+    yield np.array([2.0 ** 53, 1.0, 1.0, -2.0 ** 53])          # ties broken by the tail
+    yield np.array([1.0, 2.0 ** -53, 2.0 ** -106])             # half-way plus a sticky bit
+    yield np.array([1.0, -2.0 ** -54, 2.0 ** -107])
+    yield np.array([5e-324, 5e-324, -1e-320, 2.2250738585072014e-308])
+    yield np.array([1e300, -1e300, 1e-300, 7.0])
+    yield rng.normal(size=257) * 10.0 ** rng.integers(-30, 30, size=257)
+    v = rng.normal(size=100)
+    yield np.concatenate([v, -v, [1e-17]])                     # exact cancellation but a tail
+    yield rng.uniform(0.0, 1.0, size=2048)                    # the shape of real disorder sums
+
+
+def test_exact_sum_matches_fsum_and_rationals():
+    for a in adversarial_arrays():
+        ref = math.fsum(a.tolist())
+        assert O.exact_sum(a) == ref
+        exact = sum(Fraction(x) for x in a.tolist())
+        assert O.exact_sum(a) == float(exact)
+        perm = np.random.default_rng(3).permutation(a)
+        assert O.exact_sum(perm) == ref
+
+
+def test_leave_one_out_matches_fsum():
+    for a in adversarial_arrays():
+        col = O.ExactColumn(a)
+        idx = range(len(a)) if len(a) < 40 else range(0, len(a), 37)
+        for s in idx:
+            assert col.rounded_without(s) == math.fsum(np.delete(a, s).tolist()), s
+
+
+def test_exact_sum_non_finite():
+    assert math.isnan(O.exact_sum([1.0, math.nan, 2.0]))
+    assert math.isnan(O.exact_sum([math.inf, -math.inf]))
+    assert O.exact_sum([math.inf, 1.0, 1e308]) == math.inf
+    assert O.exact_sum([-math.inf, 1.0]) == -math.inf
+    col = O.ExactColumn([1.0, math.nan, 2.5])
+    assert col.rounded_without(1) == 3.5 and math.isnan(col.rounded_without(0))
+
+
+def test_disorder_mean_is_rounded_exact_sum_over_count():
+    rng = np.random.default_rng(5)
+    S, nT = 13, 3
+    acc = np.zeros((S, nT, O.NACC))
+    acc[..., 0] = rng.integers(1, 50, size=(S, nT)).astype(np.float64)
+    acc[..., 1:] = rng.normal(size=(S, nT, O.NACC - 1)) * acc[..., 0:1]
+    D = O.disorder_means(acc)
+    for t in range(nT):
+        for j in range(O.NACC):
+            m = [acc[s, t, j] / acc[s, t, 0] for s in range(S)]
+            assert D[t, j] == math.fsum(m) / S
+
+
+def test_observables_do_not_depend_on_sample_order():
+    rng = np.random.default_rng(9)
+    S, nT, L = 40, 4, 6
+    acc = np.zeros((S, nT, O.NACC))
+    acc[..., 0] = 100.0
+    acc[..., 1:] = rng.uniform(0.0, 1.0, size=(S, nT, O.NACC - 1)) * 100.0
+    perm = rng.permutation(S)
+    a, b = O.jackknife(acc, L), O.jackknife(acc[perm], L)
+    for k in a:
+        assert np.array_equal(a[k][0], b[k][0], equal_nan=True), k
+        assert np.array_equal(a[k][1], b[k][1], equal_nan=True), k
