@@ -172,10 +172,19 @@ ea_status ea_reset_accumulators(ea_ensemble *ens);
  * that differ (0 for a consistent state).  Synchronizing. */
 ea_status ea_check_energies(ea_ensemble *ens, int64_t *mismatches);
 
-/* Disorder averages per temperature slot over the samples with lattice size
- * L and n_T slots (eqs. 3-6), computed on the device from the accumulators.
- * out_host [n_T][EA_NOBS] binary64, columns in ea_obs order.  Samples with
- * other L or n_T are ignored; EA_EINVAL if none match. */
+/* Disorder averages per temperature slot over the selected samples of one
+ * system (eqs. 3-6), computed on the device from the accumulators.  The
+ * overline of eqs. 3-6 averages over disorder realizations of one model, so a
+ * selection must be one system: samples[0..n_samples-1] are distinct indices
+ * into the ensemble that share the lattice size, the temperature ladder (every
+ * beta, bit for bit) and the field; samples == NULL selects every sample
+ * (n_samples is then ignored).  A disorder average is the exact sum of the
+ * per-sample thermal means (accumulated sum / number of measurements), rounded
+ * once to binary64 and divided by the count, so it does not depend on the
+ * order of the samples; each observable is then evaluated in the order its
+ * formula is written.  out_host [n_T][EA_NOBS] binary64 (caller-owned),
+ * columns in ea_obs order.  EA_EINVAL for an empty, out-of-range, repeated or
+ * mixed selection (different L, ladder or field).  Synchronizing. */
 enum {
     EA_OBS_Q = 0,        /* [<q(0)>]                                          */
     EA_OBS_CHI0,         /* chi(0) = N([<q^2>] - [<q>]^2)            eq. 4     */
@@ -190,17 +199,20 @@ enum {
     EA_OBS_NSAMP,        /* number of samples averaged                         */
     EA_NOBS
 };
-ea_status ea_finalize(ea_ensemble *ens, int32_t L, int32_t n_temps, double *out_host);
+ea_status ea_finalize(ea_ensemble *ens, const int32_t *samples, int32_t n_samples, double *out_host);
 
 /* The same observables with their statistical errors from the disorder
- * average (Methods: the error is dominated by the finite number of
- * realizations): leave-one-sample-out jackknife over the samples with lattice
- * size L and n_T slots, on the device.  out_mean and out_err [n_T][EA_NOBS]
- * binary64 (caller-owned); out_mean is the full-sample estimate, out_err the
- * jackknife standard error (0 in the EA_OBS_NSAMP column).  The sample sums
- * are taken in a reduction tree, so out_mean may differ from ea_finalize in
- * the last bits.  EA_EINVAL if fewer than two samples match.  Synchronizing. */
-ea_status ea_finalize_jackknife(ea_ensemble *ens, int32_t L, int32_t n_temps, double *out_mean,
+ * average (Methods, last paragraph: the error comes from the finite number of
+ * realizations), over a selection as for ea_finalize: leave-one-sample-out
+ * jackknife on the device.  Replicate s uses the exact sum of the other
+ * samples' thermal means rounded once and divided by the count less one; the
+ * error is sqrt((S-1)/S * sum_s (O_s - Obar)^2) with Obar and the sum of
+ * squares again exact sums rounded once.  out_mean and out_err [n_T][EA_NOBS]
+ * binary64 (caller-owned); out_mean equals ea_finalize's result, out_err holds
+ * the jackknife standard errors (0 in the EA_OBS_NSAMP column).  EA_EINVAL as
+ * for ea_finalize, or if fewer than two samples are selected.
+ * Synchronizing. */
+ea_status ea_finalize_jackknife(ea_ensemble *ens, const int32_t *samples, int32_t n_samples, double *out_mean,
                                 double *out_err);
 
 /* Launch plan (see ea_plan); EA_EINVAL for values out of range. */

@@ -65,8 +65,8 @@ _SIGS = [
     ("ea_load_accumulators", ctypes.c_int, [_VP, _VP, _VP, _VP]),
     ("ea_reset_accumulators", ctypes.c_int, [_VP]),
     ("ea_check_energies", ctypes.c_int, [_VP, _VP]),
-    ("ea_finalize", ctypes.c_int, [_VP, _I32, _I32, _VP]),
-    ("ea_finalize_jackknife", ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
+    ("ea_finalize", ctypes.c_int, [_VP, _VP, _I32, _VP]),
+    ("ea_finalize_jackknife", ctypes.c_int, [_VP, _VP, _I32, _VP, _VP]),
     ("ea_set_plan", ctypes.c_int, [_VP, ctypes.POINTER(Plan)]),
     ("ea_get_plan", ctypes.c_int, [_VP, ctypes.POINTER(Plan)]),
     ("ea_autotune", ctypes.c_int, [_VP, _I32]),
@@ -264,18 +264,42 @@ class Ensemble:
         _check(load().ea_check_energies(self._h, ctypes.byref(bad)))
         return bad.value
 
-    def finalize(self, L: int, n_temps: int) -> dict:
-        out = np.zeros(n_temps * NOBS, dtype=np.float64)
-        _check(load().ea_finalize(self._h, int(L), int(n_temps), _p(out)))
-        out = out.reshape(n_temps, NOBS)
+    def systems(self) -> list:
+        """Sample indices grouped by system (lattice size, temperature ladder and
+        field), in order of first appearance: the selections ``finalize``
+        accepts."""
+        w = self.work
+        groups = {}
+        for s in range(self.S):
+            key = (int(w.L[s]), int(w.n_temps[s]), np.float32(w.h[s]).tobytes(),
+                   np.ascontiguousarray(w.beta_of(s), dtype=np.float64).tobytes())
+            groups.setdefault(key, []).append(s)
+        return list(groups.values())
+
+    def _selection(self, samples):
+        if samples is None:
+            return None, 0, int(self.nT[0])
+        sel = np.ascontiguousarray(samples, dtype=np.int32)
+        if sel.size == 0:
+            raise ValueError("empty selection")
+        return sel, int(sel.size), int(self.nT[int(sel[0])]) if 0 <= int(sel[0]) < self.S else 1
+
+    def finalize(self, samples=None) -> dict:
+        """Observables per slot of one system: ``samples`` indexes the ensemble
+        (None: every sample)."""
+        sel, n, nT = self._selection(samples)
+        out = np.zeros(nT * NOBS, dtype=np.float64)
+        _check(load().ea_finalize(self._h, None if sel is None else _p(sel), n, _p(out)))
+        out = out.reshape(nT, NOBS)
         return {k: out[:, i] for i, k in enumerate(OBS_NAMES)}
 
-    def finalize_jackknife(self, L: int, n_temps: int) -> dict:
-        """{observable: (value per slot, jackknife error per slot)}."""
-        m = np.zeros(n_temps * NOBS, dtype=np.float64)
-        e = np.zeros(n_temps * NOBS, dtype=np.float64)
-        _check(load().ea_finalize_jackknife(self._h, int(L), int(n_temps), _p(m), _p(e)))
-        m, e = m.reshape(n_temps, NOBS), e.reshape(n_temps, NOBS)
+    def finalize_jackknife(self, samples=None) -> dict:
+        """{observable: (value per slot, jackknife error per slot)} of one system."""
+        sel, n, nT = self._selection(samples)
+        m = np.zeros(nT * NOBS, dtype=np.float64)
+        e = np.zeros(nT * NOBS, dtype=np.float64)
+        _check(load().ea_finalize_jackknife(self._h, None if sel is None else _p(sel), n, _p(m), _p(e)))
+        m, e = m.reshape(nT, NOBS), e.reshape(nT, NOBS)
         return {k: (m[:, i], e[:, i]) for i, k in enumerate(OBS_NAMES)}
 
     # -- planning and timing -------------------------------------------------

@@ -36,8 +36,8 @@ __global__ void energy_kernel(const SampleDev *, const int32_t *, const int8_t *
                               int32_t *);
 __global__ void snapshot_kernel(const SampleDev *, const int32_t *, const int8_t *, const int32_t *,
                                 const int64_t *, const int32_t *, int, uint32_t *, double *);
-__global__ void finalize_kernel(const SampleDev *, int, int, int, const double *, double *);
-__global__ void finalize_jk_kernel(const SampleDev *, int, int, int, const double *, double *, double *);
+__global__ void finalize_kernel(const SampleDev *, const int32_t *, int, int, double, const double *, int, double *,
+                                double *);
 }  // namespace ea
 
 using namespace ea;
@@ -93,8 +93,10 @@ struct ea_ensemble {
     int device = 0;
     // device buffers
     DevBuf samples, items, spins, J, beta, beta32, lut, was, EJ, M, flips, swaps, acc, frames, frameE,
-        state, slot_sample, costab, sintab, scratchE, scratchM, finout, walkers, dEJ, dM, sow, Ju, mslots, Jbits;
+        state, slot_sample, costab, sintab, scratchE, scratchM, finout, walkers, dEJ, dM, sow, Ju, mslots, Jbits,
+        sel;
     int64_t frames_cap = 0;  // frames allocated
+    std::vector<double> beta_host;  // [total_slots], to check that a finalize selection is one system
     // launch classes: items sorted by lattice size, one launch per size
     struct Class {
         int L, begin, count, threads;
@@ -147,6 +149,8 @@ ea_status dalloc(ea_ensemble *e, DevBuf &b, size_t bytes)
     hipError_t st = hipMalloc(&b.p, bytes);
     if (st != hipSuccess) {
         b.p = nullptr;
+        b.bytes = 0;
+        (void)hipGetLastError();  // a failed allocation must not be read back as a later launch's error
         return fail(EA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(st));
     }
     e->device_bytes += (int64_t)bytes;
@@ -251,7 +255,7 @@ void destroy_all(ea_ensemble *e)
                       &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->frames,
                       &e->frameE, &e->state, &e->slot_sample, &e->costab, &e->sintab,
                       &e->scratchE, &e->scratchM, &e->finout, &e->walkers, &e->dEJ, &e->dM,
-                      &e->sow, &e->Ju, &e->mslots, &e->Jbits};
+                      &e->sow, &e->Ju, &e->mslots, &e->Jbits, &e->sel};
     for (DevBuf *b : bufs) dfree(*b);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
@@ -264,22 +268,37 @@ int64_t frames_for_chunk(const ea_ensemble *e, int K)
     return (int64_t)K / e->m + 2;
 }
 
-ea_status ensure_frames(ea_ensemble *e, int K)
+void drop_graphs(ea_ensemble *e)
 {
-    const int64_t need = frames_for_chunk(e, K);
-    if (need <= e->frames_cap) return EA_OK;
-    (void)hipStreamSynchronize(e->stream);
     for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : e->graph_defs) (void)hipGraphDestroy(kv.second);
     e->graphs.clear();
     e->graph_defs.clear();
+}
+
+// Grow the snapshot frames to what a chunk of K sweeps needs.  The new buffers
+// are allocated before the old ones are released, so a failed allocation
+// leaves the ensemble as it was (old frames, old capacity, graphs intact).
+ea_status ensure_frames(ea_ensemble *e, int K)
+{
+    const int64_t need = frames_for_chunk(e, K);
+    if (need <= e->frames_cap) return EA_OK;
+    DevBuf nf, nE;
+    ea_status st = dalloc(e, nf, (size_t)(need * e->frame_words) * sizeof(uint32_t));
+    if (st) return st;
+    st = dalloc(e, nE, (size_t)(need * 2 * e->total_slots) * sizeof(double));
+    if (st) {
+        e->device_bytes -= (int64_t)nf.bytes;
+        dfree(nf);
+        return st;
+    }
+    (void)hipStreamSynchronize(e->stream);  // queued work may still use the old frames
+    drop_graphs(e);                         // captured graphs hold the old addresses
     e->device_bytes -= (int64_t)(e->frames.bytes + e->frameE.bytes);
     dfree(e->frames);
     dfree(e->frameE);
-    ea_status st = dalloc(e, e->frames, (size_t)(need * e->frame_words) * sizeof(uint32_t));
-    if (st) return st;
-    st = dalloc(e, e->frameE, (size_t)(need * 2 * e->total_slots) * sizeof(double));
-    if (st) return st;
+    e->frames = nf;
+    e->frameE = nE;
     e->frames_cap = need;
     return EA_OK;
 }
@@ -647,7 +666,7 @@ ea_status plan_samples(const ea_desc *d, size_t lds_max, std::vector<SampleHost>
 // The persistent device buffers, in arena order (ea_bind_buffers), and their
 // sizes.  The snapshot frames (sized by the plan's chunk) and the scratch of
 // ea_check_energies stay outside.
-constexpr int NARENA = 25;
+constexpr int NARENA = 26;
 constexpr size_t ARENA_ALIGN = 256;
 
 void arena_buffers(ea_ensemble *e, DevBuf *b[NARENA])
@@ -655,7 +674,7 @@ void arena_buffers(ea_ensemble *e, DevBuf *b[NARENA])
     DevBuf *list[NARENA] = {&e->samples, &e->items, &e->spins, &e->J, &e->beta, &e->beta32, &e->lut,
                             &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->state,
                             &e->slot_sample, &e->costab, &e->sintab, &e->finout, &e->dEJ, &e->dM,
-                            &e->sow, &e->walkers, &e->Ju, &e->mslots, &e->Jbits};
+                            &e->sow, &e->walkers, &e->Ju, &e->mslots, &e->Jbits, &e->sel};
     for (int k = 0; k < NARENA; ++k) b[k] = list[k];
 }
 
@@ -671,7 +690,7 @@ void arena_sizes(int S, int jkind, const SampleTotals &t, size_t sz[NARENA])
         sizeof(double) * (MAX_L + 1) * MAX_L, sizeof(double) * 2 * MAX_T * EA_NOBS, sizeof(int64_t) * 2 * TS,
         sizeof(int32_t) * 2 * TS, sizeof(int32_t) * 2 * TS, sizeof(int32_t) * (size_t)t.hbm_walkers,
         t.any_hbm && jkind == EA_J_GAUSS_F32 ? sizeof(int32_t) * (size_t)t.J_elems : 0, sizeof(int32_t) * TS,
-        sizeof(uint32_t) * (size_t)t.jbits_words};
+        sizeof(uint32_t) * (size_t)t.jbits_words, sizeof(int32_t) * S};
     for (int k = 0; k < NARENA; ++k) sz[k] = sizes[k];
 }
 
@@ -720,6 +739,64 @@ ea_status run_sweeps(ea_ensemble *e, int64_t n, bool unbatched)
         e->sweep += K;
         n -= K;
     }
+    return EA_OK;
+}
+
+// The selection of a finalize call: n indices into the ensemble (every
+// sample when sel is NULL), distinct, all of one system -- the same lattice
+// size, temperature ladder (every beta, bit for bit) and field.  Copies it to
+// the device.
+ea_status finalize_selection(ea_ensemble *e, const int32_t *sel, int32_t n, int min_count, int *count)
+{
+    std::vector<int32_t> idx;
+    if (sel) {
+        if (n < 1 || n > e->S) return fail(EA_EINVAL, "selection size %d outside [1, %d]", n, e->S);
+        idx.assign(sel, sel + n);
+    } else {
+        idx.resize(e->S);
+        for (int s = 0; s < e->S; ++s) idx[s] = s;
+    }
+    if ((int)idx.size() < min_count)
+        return fail(EA_EINVAL, "%zu samples selected; at least %d needed", idx.size(), min_count);
+    std::vector<char> seen(e->S, 0);
+    for (int32_t s : idx) {
+        if (s < 0 || s >= e->S) return fail(EA_EINVAL, "sample index %d outside [0, %d)", s, e->S);
+        if (seen[s]) return fail(EA_EINVAL, "sample %d selected twice", s);
+        seen[s] = 1;
+    }
+    const SampleHost &a = e->smp[idx[0]];
+    for (int32_t s : idx) {
+        const SampleHost &b = e->smp[s];
+        if (b.L != a.L || b.nT != a.nT)
+            return fail(EA_EINVAL, "samples %d and %d differ in lattice size or ladder length", idx[0], s);
+        if (std::memcmp(&b.h, &a.h, sizeof a.h) != 0)
+            return fail(EA_EINVAL, "samples %d and %d are at different fields", idx[0], s);
+        if (std::memcmp(&e->beta_host[b.slot_off], &e->beta_host[a.slot_off], sizeof(double) * a.nT) != 0)
+            return fail(EA_EINVAL, "samples %d and %d have different temperature ladders", idx[0], s);
+    }
+    HIP_TRY(e, hipMemcpyAsync(e->sel.p, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice,
+                              e->stream));
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    *count = (int)idx.size();
+    return EA_OK;
+}
+
+ea_status run_finalize(ea_ensemble *e, const int32_t *sel, int32_t n, double *out_mean, double *out_err)
+{
+    const bool jk = out_err != nullptr;
+    int count = 0;
+    ea_status st = finalize_selection(e, sel, n, jk ? 2 : 1, &count);
+    if (st) return st;
+    const int s0 = sel ? sel[0] : 0;
+    const int L = e->smp[s0].L, nT = e->smp[s0].nT;
+    const double two_sin = 2.0 * std::sin(M_PI / (double)L);
+    double *dm = (double *)e->finout.p, *de = dm + (size_t)MAX_T * EA_NOBS;
+    hipLaunchKernelGGL(finalize_kernel, dim3(nT), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
+                       (const int32_t *)e->sel.p, count, L, two_sin, (const double *)e->acc.p, jk ? 1 : 0, dm, de);
+    HIP_TRY(e, hipGetLastError());
+    HIP_TRY(e, hipMemcpyAsync(out_mean, dm, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
+    if (jk) HIP_TRY(e, hipMemcpyAsync(out_err, de, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
     return EA_OK;
 }
 
@@ -833,6 +910,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     std::vector<char> Jsub((size_t)e->J_elems * jsz);
     std::vector<double> beta(e->total_slots);
     std::vector<float> beta32(e->total_slots);
+    e->beta_host.assign(d->beta, d->beta + e->total_slots);
     std::vector<uint32_t> lut(e->total_slots * 14);
     std::vector<int32_t> was(2 * e->total_slots);
     for (int s = 0; s < S; ++s) {
@@ -958,7 +1036,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
             sizeof(int32_t) * was.size(), sz[8], sz[9], sz[10], sz[11], sz[12], sz[13],
             sizeof(int32_t) * slot_sample.size(), sizeof(double) * costab.size(), sizeof(double) * sintab.size(),
             sz[17], sz[18], sz[19], sz[20], sizeof(int32_t) * wtab.size(), sizeof(int32_t) * Ju.size(),
-            sizeof(int32_t) * mslots.size(), sizeof(uint32_t) * Jbits.size()};
+            sizeof(int32_t) * mslots.size(), sizeof(uint32_t) * Jbits.size(), sz[25]};
         DevBuf *bufs[NARENA];
         arena_buffers(e, bufs);
         for (int k = 0; k < NARENA; ++k) {
@@ -1188,39 +1266,19 @@ ea_status ea_check_energies(ea_ensemble *e, int64_t *mismatches)
     return EA_OK;
 }
 
-ea_status ea_finalize(ea_ensemble *e, int32_t L, int32_t nT, double *out)
+ea_status ea_finalize(ea_ensemble *e, const int32_t *samples, int32_t n_samples, double *out)
 {
     if (!usable(e)) return EA_ESTATE;
     if (!out) return fail(EA_EINVAL, "out is NULL");
-    if (nT < 1 || nT > MAX_T) return fail(EA_EINVAL, "n_temps out of range");
-    bool any = false;
-    for (const auto &h : e->smp) any |= (h.L == L && h.nT == nT);
-    if (!any) return fail(EA_EINVAL, "no sample with L=%d and %d temperatures", L, nT);
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, e->stream, (const SampleDev *)e->samples.p, e->S, L, nT,
-                       (const double *)e->acc.p, (double *)e->finout.p);
-    HIP_TRY(e, hipGetLastError());
-    HIP_TRY(e, hipMemcpyAsync(out, e->finout.p, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
-    HIP_TRY(e, hipStreamSynchronize(e->stream));
-    return EA_OK;
+    return run_finalize(e, samples, n_samples, out, nullptr);
 }
 
-ea_status ea_finalize_jackknife(ea_ensemble *e, int32_t L, int32_t nT, double *out_mean, double *out_err)
+ea_status ea_finalize_jackknife(ea_ensemble *e, const int32_t *samples, int32_t n_samples, double *out_mean,
+                                double *out_err)
 {
     if (!usable(e)) return EA_ESTATE;
     if (!out_mean || !out_err) return fail(EA_EINVAL, "output is NULL");
-    if (nT < 1 || nT > MAX_T) return fail(EA_EINVAL, "n_temps out of range");
-    int matches = 0;
-    for (const auto &h : e->smp) matches += (h.L == L && h.nT == nT);
-    if (matches < 2) return fail(EA_EINVAL, "%d samples with L=%d and %d temperatures; the jackknife needs two",
-                                 matches, L, nT);
-    double *dm = (double *)e->finout.p, *de = dm + (size_t)MAX_T * EA_NOBS;
-    hipLaunchKernelGGL(finalize_jk_kernel, dim3(nT), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p, e->S,
-                       L, nT, (const double *)e->acc.p, dm, de);
-    HIP_TRY(e, hipGetLastError());
-    HIP_TRY(e, hipMemcpyAsync(out_mean, dm, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
-    HIP_TRY(e, hipMemcpyAsync(out_err, de, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
-    HIP_TRY(e, hipStreamSynchronize(e->stream));
-    return EA_OK;
+    return run_finalize(e, samples, n_samples, out_mean, out_err);
 }
 
 ea_status ea_set_plan(ea_ensemble *e, const ea_plan *p)
@@ -1233,6 +1291,7 @@ ea_status ea_set_plan(ea_ensemble *e, const ea_plan *p)
     for (const auto &h : e->smp)
         if ((int64_t)p->chunk * h.N >= ((int64_t)1 << 31))
             return fail(EA_EINVAL, "chunk too long for the per-chunk flip counters");
+    if (p->threads != e->plan.threads) drop_graphs(e);  // captured graphs embed the launch shape
     e->plan = *p;
     return EA_OK;
 }
@@ -1394,11 +1453,7 @@ ea_status ea_bind_buffers(ea_ensemble *e, void *const *device_ptrs, size_t arena
         bufs[k]->p = bytes ? base + off[k] : nullptr;
         bufs[k]->owned = false;
     }
-    // captured graphs hold the old addresses
-    for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (auto &kv : e->graph_defs) (void)hipGraphDestroy(kv.second);
-    e->graphs.clear();
-    e->graph_defs.clear();
+    drop_graphs(e);  // captured graphs hold the old addresses
     e->bound = true;
     return EA_OK;
 }

@@ -26,6 +26,7 @@
 // own LDS layouts.  This file also holds the HBM-resident tier, the overlap
 // measurement, the finalize and the setup and check kernels.
 #include "ea_device.hpp"
+#include "ea_exact.hpp"
 #include "ea_item.hpp"
 #include "ea_types.hpp"
 #include "ea_update.hpp"
@@ -1072,8 +1073,9 @@ __global__ void __launch_bounds__(256) snapshot_kernel(const SampleDev *samples,
 }
 
 // Observables of eqs. 3-6 from disorder-averaged thermal means D[36] (column
-// order of ea_obs, without the sample count).
-__device__ __forceinline__ void observables_of(const double *D, int L, double *o)
+// order of the accumulators), each formula evaluated in the order written,
+// one rounding per binary64 operation.  two_sin = 2 sin(pi/L) (host libm).
+__device__ __forceinline__ void observables_of(const double *D, int L, double two_sin, double *o)
 {
     const double N = (double)L * L * L;
     const double q1 = D[1], q2 = D[2], q3 = D[3], q4 = D[4], Q = q1;
@@ -1092,119 +1094,108 @@ __device__ __forceinline__ void observables_of(const double *D, int L, double *o
     o[2] = chik;
     o[3] = chik2;
     o[4] = 0.5 * (3.0 - c4 / (c2 * c2));
-    o[5] = sqrt(chi0 / chik - 1.0) / (2.0 * sin(3.141592653589793 / (double)L));
+    o[5] = sqrt(chi0 / chik - 1.0) / two_sin;
     o[6] = chik / chik2;
     o[7] = chi0 / chik;
     o[8] = D[32];
     o[9] = D[34];
 }
 
-// Disorder averages per slot over the samples of one lattice size and ladder
-// length (eqs. 3-6).  Single workgroup; thread t handles slot t and sums over
-// samples in sample order.
-__global__ void finalize_kernel(const SampleDev *samples, int S, int L, int nT, const double *acc,
-                                double *out)
-{
-    const int t = threadIdx.x;
-    if (t >= nT) return;
-    double D[NACC];
-    for (int j = 0; j < NACC; ++j) D[j] = 0.0;
-    int cnt = 0;
-    for (int s = 0; s < S; ++s) {
-        const SampleDev d = samples[s];
-        if (d.L != L || d.n_T != nT) continue;
-        const double *a = acc + ((size_t)d.slot_off + t) * NACC;
-        for (int j = 0; j < NACC; ++j) D[j] += a[j] / a[0];
-        ++cnt;
-    }
-    double *o = out + (size_t)t * 11;
-    o[10] = (double)cnt;
-    if (cnt == 0) return;
-    for (int j = 0; j < NACC; ++j) D[j] /= (double)cnt;
-    observables_of(D, L, o);
-}
+constexpr int NOBS_VAL = 10;  // observables per slot (the count column aside)
 
-// Leave-one-sample-out jackknife of the same observables (the statistical
-// error comes from the disorder average).  One workgroup per slot; threads
-// stride over samples.  With M = sum of the per-sample thermal means over the
-// cnt matching samples, replicate s uses (M - m_s) / (cnt - 1); the error is
-// sqrt((cnt - 1)/cnt sum_s (O_s - mean_s O_s)^2), two passes.  The central
-// value is the full-sample estimate M / cnt.
-__device__ __forceinline__ double block_sum_f64(double v, double *red)
+// Disorder averages (eqs. 3-6) and, with jk, leave-one-sample-out jackknife
+// errors (Methods, last paragraph) per temperature slot over the S selected
+// samples sel[0..S-1] of one system.  One workgroup per slot.
+//  1. Column j of the slot: exact sum over samples of the thermal mean
+//     acc[j] / acc[0], kept normalized in LDS; D[j] = (rounded sum) / S.
+//  2. Observables of D: the central values.
+//  3. Replicate s: D_s[j] = (rounded exact sum less sample s's value) / (S-1),
+//     observables O_s; exact sums over s of O_s give the replicate mean
+//     Obar = (rounded sum) / S, then exact sums of (O_s - Obar)^2 give
+//     err = sqrt((S-1)/S * rounded sum).  Replicates are recomputed in the
+//     second pass (the same arithmetic), so nothing is stored per sample.
+__global__ void __launch_bounds__(256) finalize_kernel(const SampleDev *samples, const int32_t *sel, int S, int L,
+                                                       double two_sin, const double *acc, int jk, double *mean_out,
+                                                       double *err_out)
 {
-    const int tid = threadIdx.x, T = blockDim.x;
-    red[tid] = v;
-    __syncthreads();
-    for (int w = T / 2; w >= 1; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
-}
-
-__global__ void __launch_bounds__(256) finalize_jk_kernel(const SampleDev *samples, int S, int L, int nT,
-                                                          const double *acc, double *mean_out, double *err_out)
-{
-    __shared__ double red[256];
-    __shared__ double Msum[NACC];
-    __shared__ double Obar[10];
+    __shared__ uint32_t dig[NACC][XL];   // normalized digits of each column's exact sum
+    __shared__ int32_t sgn[NACC];        // its final carry (0 or -1)
+    __shared__ int32_t spec[NACC][3];    // its NaN, +inf, -inf counts
+    __shared__ double D[NACC];
+    __shared__ unsigned long long osum[NOBS_VAL][XL];  // exact sums over replicates
+    __shared__ int32_t ospec[NOBS_VAL][3];
+    __shared__ double obar[NOBS_VAL];
     const int t = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
-    double part[NACC];
-    for (int j = 0; j < NACC; ++j) part[j] = 0.0;
-    int cnt = 0;
-    for (int s = tid; s < S; s += T) {
-        const SampleDev d = samples[s];
-        if (d.L != L || d.n_T != nT) continue;
-        const double *a = acc + ((size_t)d.slot_off + t) * NACC;
-        for (int j = 0; j < NACC; ++j) part[j] += a[j] / a[0];
-        ++cnt;
+    if (tid < NACC) {
+        int64_t lim[XL];
+        for (int k = 0; k < XL; ++k) lim[k] = 0;
+        int sp[3] = {0, 0, 0};
+        for (int i = 0; i < S; ++i) {
+            const double *a = acc + ((size_t)samples[sel[i]].slot_off + t) * NACC;
+            const double m = a[tid] / a[0];
+            const int c = exact_class(m);
+            if (c >= 0) ++sp[c];
+            else exact_add(lim, m);
+        }
+        const int64_t carry = exact_normalize(lim);
+        for (int k = 0; k < XL; ++k) dig[tid][k] = (uint32_t)lim[k];
+        sgn[tid] = (int32_t)carry;
+        for (int c = 0; c < 3; ++c) spec[tid][c] = sp[c];
+        double v;
+        if (!exact_special(sp[0], sp[1], sp[2], &v)) v = exact_round_normalized(lim, carry);
+        D[tid] = v / (double)S;
     }
-    for (int j = 0; j < NACC; ++j) {
-        const double v = block_sum_f64(part[j], red);
-        if (tid == 0) Msum[j] = v;
-    }
-    const int total = (int)block_sum_f64((double)cnt, red);
     __syncthreads();
-    if (total < 2) {
-        if (tid == 0)
-            for (int k = 0; k < 11; ++k) {
-                mean_out[(size_t)t * 11 + k] = k == 10 ? (double)total : 0.0;
-                err_out[(size_t)t * 11 + k] = 0.0;
-            }
-        return;
-    }
     if (tid == 0) {
-        double D[NACC], o[10];
-        for (int j = 0; j < NACC; ++j) D[j] = Msum[j] / (double)total;
-        observables_of(D, L, o);
-        for (int k = 0; k < 10; ++k) mean_out[(size_t)t * 11 + k] = o[k];
-        mean_out[(size_t)t * 11 + 10] = (double)total;
-        err_out[(size_t)t * 11 + 10] = 0.0;
+        double o[NOBS_VAL];
+        observables_of(D, L, two_sin, o);
+        for (int k = 0; k < NOBS_VAL; ++k) mean_out[(size_t)t * (NOBS_VAL + 1) + k] = o[k];
+        mean_out[(size_t)t * (NOBS_VAL + 1) + NOBS_VAL] = (double)S;
     }
+    if (!jk) return;
     for (int pass = 0; pass < 2; ++pass) {
-        double acc_o[10];
-        for (int k = 0; k < 10; ++k) acc_o[k] = 0.0;
-        for (int s = tid; s < S; s += T) {
-            const SampleDev d = samples[s];
-            if (d.L != L || d.n_T != nT) continue;
-            const double *a = acc + ((size_t)d.slot_off + t) * NACC;
-            double D[NACC], o[10];
-            for (int j = 0; j < NACC; ++j) D[j] = (Msum[j] - a[j] / a[0]) / (double)(total - 1);
-            observables_of(D, L, o);
-            for (int k = 0; k < 10; ++k) {
-                const double dv = pass == 0 ? o[k] : o[k] - Obar[k];
-                acc_o[k] += pass == 0 ? dv : dv * dv;
+        for (int i = tid; i < NOBS_VAL * XL; i += T) (&osum[0][0])[i] = 0ull;
+        for (int i = tid; i < NOBS_VAL * 3; i += T) (&ospec[0][0])[i] = 0;
+        __syncthreads();
+        for (int i = tid; i < S; i += T) {
+            const double *a = acc + ((size_t)samples[sel[i]].slot_off + t) * NACC;
+            double Ds[NACC], o[NOBS_VAL];
+            for (int j = 0; j < NACC; ++j) {
+                const double m = a[j] / a[0];
+                const int c = exact_class(m);
+                const int n0 = spec[j][0] - (c == 0), n1 = spec[j][1] - (c == 1), n2 = spec[j][2] - (c == 2);
+                double v;
+                if (!exact_special(n0, n1, n2, &v)) {
+                    int64_t lim[XL];
+                    for (int k = 0; k < XL; ++k) lim[k] = (int64_t)dig[j][k];
+                    lim[XL - 1] += (int64_t)sgn[j] * ((int64_t)1 << 32);
+                    if (c < 0) exact_add(lim, m, true);
+                    v = exact_round(lim);
+                }
+                Ds[j] = v / (double)(S - 1);
+            }
+            observables_of(Ds, L, two_sin, o);
+            for (int k = 0; k < NOBS_VAL; ++k) {
+                double x = o[k];
+                if (pass == 1) {
+                    const double dv = x - obar[k];
+                    x = dv * dv;
+                }
+                const int c = exact_class(x);
+                if (c >= 0) atomicAdd(&ospec[k][c], 1);
+                else exact_add_atomic(osum[k], x);
             }
         }
-        for (int k = 0; k < 10; ++k) {
-            const double v = block_sum_f64(acc_o[k], red);
-            if (tid == 0) {
-                if (pass == 0) Obar[k] = v / (double)total;
-                else err_out[(size_t)t * 11 + k] = sqrt((double)(total - 1) / (double)total * v);
-            }
+        __syncthreads();
+        if (tid < NOBS_VAL) {
+            int64_t lim[XL];
+            for (int k = 0; k < XL; ++k) lim[k] = (int64_t)osum[tid][k];
+            double v;
+            if (!exact_special(ospec[tid][0], ospec[tid][1], ospec[tid][2], &v)) v = exact_round(lim);
+            if (pass == 0) obar[tid] = v / (double)S;
+            else err_out[(size_t)t * (NOBS_VAL + 1) + tid] = sqrt((double)(S - 1) / (double)S * v);
         }
+        if (pass == 1 && tid == 0) err_out[(size_t)t * (NOBS_VAL + 1) + NOBS_VAL] = 0.0;
         __syncthreads();
     }
 }

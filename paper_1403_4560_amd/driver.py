@@ -108,7 +108,7 @@ def run_log_binned(work: W.Workload, log2_sweeps: int, first_bin: int | None = N
             acc0 = np.stack([a[:, 0] for a in ms["acc"]])
             if not np.all(acc0 == nmeas):
                 raise RuntimeError("bin %d: expected %d measurements per slot" % (k, nmeas))
-            obs = ens.finalize_jackknife(L, n_T)
+            obs = ens.finalize_jackknife()
             swaps = np.stack(ms["swaps"]).astype(np.float64)     # [S][2][n_T]
             flips = np.stack(ms["flips"]).astype(np.float64)
             attempts = np.array([exchange_attempts(lo, hi, t) for t in range(n_T)], dtype=np.float64)
