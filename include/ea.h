@@ -215,6 +215,20 @@ ea_status ea_finalize(ea_ensemble *ens, const int32_t *samples, int32_t n_sample
 ea_status ea_finalize_jackknife(ea_ensemble *ens, const int32_t *samples, int32_t n_samples, double *out_mean,
                                 double *out_err);
 
+/* ea_finalize_jackknife for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, results and errors, bit-identical to
+ * ea_finalize_jackknife, but no device or host allocation.  The jackknife
+ * replicates (n_temps x selected samples x 10 doubles) go to a fixed scratch
+ * array of 8 MiB that every device the library runs on holds until the
+ * process ends (its address is looked up when an ensemble is created on that
+ * device); EA_EINVAL if n_temps x samples exceeds 104857.  Every call on one
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race and must be serialized by the caller.
+ * EA_EDEVICE if the scratch address could not be obtained.  Synchronizing. */
+ea_status ea_finalize_jackknife_noalloc(ea_ensemble *ens, const int32_t *samples, int32_t n_samples,
+                                        double *out_mean, double *out_err);
+
 /* Launch plan (see ea_plan); EA_EINVAL for values out of range. */
 ea_status ea_set_plan(ea_ensemble *ens, const ea_plan *plan);
 ea_status ea_get_plan(const ea_ensemble *ens, ea_plan *plan);

@@ -67,6 +67,7 @@ _SIGS = [
     ("ea_check_energies", ctypes.c_int, [_VP, _VP]),
     ("ea_finalize", ctypes.c_int, [_VP, _VP, _I32, _VP]),
     ("ea_finalize_jackknife", ctypes.c_int, [_VP, _VP, _I32, _VP, _VP]),
+    ("ea_finalize_jackknife_noalloc", ctypes.c_int, [_VP, _VP, _I32, _VP, _VP]),
     ("ea_set_plan", ctypes.c_int, [_VP, ctypes.POINTER(Plan)]),
     ("ea_get_plan", ctypes.c_int, [_VP, ctypes.POINTER(Plan)]),
     ("ea_autotune", ctypes.c_int, [_VP, _I32]),
@@ -293,12 +294,14 @@ class Ensemble:
         out = out.reshape(nT, NOBS)
         return {k: out[:, i] for i, k in enumerate(OBS_NAMES)}
 
-    def finalize_jackknife(self, samples=None) -> dict:
-        """{observable: (value per slot, jackknife error per slot)} of one system."""
+    def finalize_jackknife(self, samples=None, noalloc=False) -> dict:
+        """{observable: (value per slot, jackknife error per slot)} of one system.
+        noalloc: use the entry point that allocates nothing (fixed scratch)."""
         sel, n, nT = self._selection(samples)
         m = np.zeros(nT * NOBS, dtype=np.float64)
         e = np.zeros(nT * NOBS, dtype=np.float64)
-        _check(load().ea_finalize_jackknife(self._h, None if sel is None else _p(sel), n, _p(m), _p(e)))
+        fn = load().ea_finalize_jackknife_noalloc if noalloc else load().ea_finalize_jackknife
+        _check(fn(self._h, None if sel is None else _p(sel), n, _p(m), _p(e)))
         m, e = m.reshape(nT, NOBS), e.reshape(nT, NOBS)
         return {k: (m[:, i], e[:, i]) for i, k in enumerate(OBS_NAMES)}
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -37,10 +38,45 @@ __global__ void energy_kernel(const SampleDev *, const int32_t *, const int8_t *
 __global__ void snapshot_kernel(const SampleDev *, const int32_t *, const int8_t *, const int32_t *,
                                 const int64_t *, const int32_t *, int, uint32_t *, double *);
 __global__ void finalize_kernel(const SampleDev *, const int32_t *, int, int, double, const double *, int, double *,
-                                double *);
+                                double *, double *);
 }  // namespace ea
 
 using namespace ea;
+
+// No-allocation scratch (ea_finalize_jackknife_noalloc): a file-scope device
+// array, one copy per device, holding the jackknife replicates.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in,
+// not a device address): the device address is looked up once per device,
+// with that device current, and kept in g_scratch_ptr.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)1 << 20;  // 8 MiB per device
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEVICES];
+bool g_scratch_looked_up[SCRATCH_MAX_DEVICES];
+
+// The device address of this device's scratch array, or NULL if the lookup
+// failed (then the no-allocation entry point reports an error).  Called with
+// the device current.
+void *scratch_address(int dev)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_looked_up[dev]) {
+        void *ptr = nullptr;
+        const hipError_t st = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (st != hipSuccess) {
+            (void)hipGetLastError();
+            ptr = nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+        g_scratch_looked_up[dev] = true;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
 
 namespace {
 
@@ -97,6 +133,10 @@ struct ea_ensemble {
         sel;
     int64_t frames_cap = 0;  // frames allocated
     std::vector<double> beta_host;  // [total_slots], to check that a finalize selection is one system
+    std::vector<int32_t> sel_idx;   // [S] a finalize call's selection (no allocation per call)
+    std::vector<char> sel_seen;     // [S]
+    DevBuf jkrep;                   // jackknife replicates, grown on demand
+    void *static_scratch = nullptr; // this device's no-allocation scratch (0: not available)
     // launch classes: items sorted by lattice size, one launch per size
     struct Class {
         int L, begin, count, threads;
@@ -255,7 +295,7 @@ void destroy_all(ea_ensemble *e)
                       &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->frames,
                       &e->frameE, &e->state, &e->slot_sample, &e->costab, &e->sintab,
                       &e->scratchE, &e->scratchM, &e->finout, &e->walkers, &e->dEJ, &e->dM,
-                      &e->sow, &e->Ju, &e->mslots, &e->Jbits, &e->sel};
+                      &e->sow, &e->Ju, &e->mslots, &e->Jbits, &e->sel, &e->jkrep};
     for (DevBuf *b : bufs) dfree(*b);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
@@ -745,54 +785,73 @@ ea_status run_sweeps(ea_ensemble *e, int64_t n, bool unbatched)
 // The selection of a finalize call: n indices into the ensemble (every
 // sample when sel is NULL), distinct, all of one system -- the same lattice
 // size, temperature ladder (every beta, bit for bit) and field.  Copies it to
-// the device.
+// the device.  Uses only the ensemble's own host buffers (no allocation).
 ea_status finalize_selection(ea_ensemble *e, const int32_t *sel, int32_t n, int min_count, int *count)
 {
-    std::vector<int32_t> idx;
+    int32_t *idx = e->sel_idx.data();
+    int cnt = e->S;
     if (sel) {
         if (n < 1 || n > e->S) return fail(EA_EINVAL, "selection size %d outside [1, %d]", n, e->S);
-        idx.assign(sel, sel + n);
+        cnt = n;
+        for (int i = 0; i < n; ++i) idx[i] = sel[i];
     } else {
-        idx.resize(e->S);
         for (int s = 0; s < e->S; ++s) idx[s] = s;
     }
-    if ((int)idx.size() < min_count)
-        return fail(EA_EINVAL, "%zu samples selected; at least %d needed", idx.size(), min_count);
-    std::vector<char> seen(e->S, 0);
-    for (int32_t s : idx) {
+    if (cnt < min_count) return fail(EA_EINVAL, "%d samples selected; at least %d needed", cnt, min_count);
+    std::fill(e->sel_seen.begin(), e->sel_seen.end(), 0);
+    for (int i = 0; i < cnt; ++i) {
+        const int32_t s = idx[i];
         if (s < 0 || s >= e->S) return fail(EA_EINVAL, "sample index %d outside [0, %d)", s, e->S);
-        if (seen[s]) return fail(EA_EINVAL, "sample %d selected twice", s);
-        seen[s] = 1;
+        if (e->sel_seen[s]) return fail(EA_EINVAL, "sample %d selected twice", s);
+        e->sel_seen[s] = 1;
     }
     const SampleHost &a = e->smp[idx[0]];
-    for (int32_t s : idx) {
-        const SampleHost &b = e->smp[s];
+    for (int i = 0; i < cnt; ++i) {
+        const SampleHost &b = e->smp[idx[i]];
         if (b.L != a.L || b.nT != a.nT)
-            return fail(EA_EINVAL, "samples %d and %d differ in lattice size or ladder length", idx[0], s);
+            return fail(EA_EINVAL, "samples %d and %d differ in lattice size or ladder length", idx[0], idx[i]);
         if (std::memcmp(&b.h, &a.h, sizeof a.h) != 0)
-            return fail(EA_EINVAL, "samples %d and %d are at different fields", idx[0], s);
+            return fail(EA_EINVAL, "samples %d and %d are at different fields", idx[0], idx[i]);
         if (std::memcmp(&e->beta_host[b.slot_off], &e->beta_host[a.slot_off], sizeof(double) * a.nT) != 0)
-            return fail(EA_EINVAL, "samples %d and %d have different temperature ladders", idx[0], s);
+            return fail(EA_EINVAL, "samples %d and %d have different temperature ladders", idx[0], idx[i]);
     }
-    HIP_TRY(e, hipMemcpyAsync(e->sel.p, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice,
-                              e->stream));
+    HIP_TRY(e, hipMemcpyAsync(e->sel.p, idx, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, e->stream));
     HIP_TRY(e, hipStreamSynchronize(e->stream));
-    *count = (int)idx.size();
+    *count = cnt;
     return EA_OK;
 }
 
-ea_status run_finalize(ea_ensemble *e, const int32_t *sel, int32_t n, double *out_mean, double *out_err)
+// Doubles of jackknife replicate scratch a selection of count samples with
+// nT slots needs (10 observables per replicate and slot).
+size_t jk_rep_doubles(int nT, int count) { return (size_t)nT * (size_t)count * 10; }
+
+// rep: replicate scratch for the jackknife (NULL: the library's own buffer,
+// grown here on demand).
+ea_status run_finalize(ea_ensemble *e, const int32_t *sel, int32_t n, double *out_mean, double *out_err,
+                       double *rep)
 {
     const bool jk = out_err != nullptr;
     int count = 0;
     ea_status st = finalize_selection(e, sel, n, jk ? 2 : 1, &count);
     if (st) return st;
-    const int s0 = sel ? sel[0] : 0;
+    const int s0 = e->sel_idx[0];
     const int L = e->smp[s0].L, nT = e->smp[s0].nT;
+    if (jk && !rep) {
+        const size_t need = jk_rep_doubles(nT, count) * sizeof(double);
+        if (e->jkrep.bytes < need) {
+            DevBuf nb;
+            if ((st = dalloc(e, nb, need)) != EA_OK) return st;
+            e->device_bytes -= (int64_t)e->jkrep.bytes;
+            dfree(e->jkrep);
+            e->jkrep = nb;
+        }
+        rep = (double *)e->jkrep.p;
+    }
     const double two_sin = 2.0 * std::sin(M_PI / (double)L);
     double *dm = (double *)e->finout.p, *de = dm + (size_t)MAX_T * EA_NOBS;
     hipLaunchKernelGGL(finalize_kernel, dim3(nT), dim3(256), 0, e->stream, (const SampleDev *)e->samples.p,
-                       (const int32_t *)e->sel.p, count, L, two_sin, (const double *)e->acc.p, jk ? 1 : 0, dm, de);
+                       (const int32_t *)e->sel.p, count, L, two_sin, (const double *)e->acc.p, jk ? 1 : 0, rep, dm,
+                       de);
     HIP_TRY(e, hipGetLastError());
     HIP_TRY(e, hipMemcpyAsync(out_mean, dm, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
     if (jk) HIP_TRY(e, hipMemcpyAsync(out_err, de, sizeof(double) * nT * EA_NOBS, hipMemcpyDeviceToHost, e->stream));
@@ -911,6 +970,9 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     std::vector<double> beta(e->total_slots);
     std::vector<float> beta32(e->total_slots);
     e->beta_host.assign(d->beta, d->beta + e->total_slots);
+    e->sel_idx.assign(S, 0);
+    e->sel_seen.assign(S, 0);
+    e->static_scratch = scratch_address(e->device);
     std::vector<uint32_t> lut(e->total_slots * 14);
     std::vector<int32_t> was(2 * e->total_slots);
     for (int s = 0; s < S; ++s) {
@@ -1270,7 +1332,7 @@ ea_status ea_finalize(ea_ensemble *e, const int32_t *samples, int32_t n_samples,
 {
     if (!usable(e)) return EA_ESTATE;
     if (!out) return fail(EA_EINVAL, "out is NULL");
-    return run_finalize(e, samples, n_samples, out, nullptr);
+    return run_finalize(e, samples, n_samples, out, nullptr, nullptr);
 }
 
 ea_status ea_finalize_jackknife(ea_ensemble *e, const int32_t *samples, int32_t n_samples, double *out_mean,
@@ -1278,7 +1340,26 @@ ea_status ea_finalize_jackknife(ea_ensemble *e, const int32_t *samples, int32_t 
 {
     if (!usable(e)) return EA_ESTATE;
     if (!out_mean || !out_err) return fail(EA_EINVAL, "output is NULL");
-    return run_finalize(e, samples, n_samples, out_mean, out_err);
+    return run_finalize(e, samples, n_samples, out_mean, out_err, nullptr);
+}
+
+ea_status ea_finalize_jackknife_noalloc(ea_ensemble *e, const int32_t *samples, int32_t n_samples,
+                                        double *out_mean, double *out_err)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (!out_mean || !out_err) return fail(EA_EINVAL, "output is NULL");
+    if (!e->static_scratch)
+        return fail(EA_EDEVICE, "the no-allocation scratch of device %d is not available", e->device);
+    // the selection's shape, for the size check before anything is queued
+    int count = samples ? n_samples : e->S;
+    int s0 = samples ? (n_samples >= 1 ? samples[0] : -1) : 0;
+    if (s0 < 0 || s0 >= e->S || count < 1) return fail(EA_EINVAL, "empty or out-of-range selection");
+    const size_t need = jk_rep_doubles(e->smp[s0].nT, count);
+    if (need > NOALLOC_SCRATCH_DOUBLES)
+        return fail(EA_EINVAL, "selection needs %zu doubles of replicate scratch; the no-allocation limit is %zu "
+                               "(n_temps x samples <= %zu)", need, (size_t)NOALLOC_SCRATCH_DOUBLES,
+                    (size_t)NOALLOC_SCRATCH_DOUBLES / 10);
+    return run_finalize(e, samples, n_samples, out_mean, out_err, (double *)e->static_scratch);
 }
 
 ea_status ea_set_plan(ea_ensemble *e, const ea_plan *p)

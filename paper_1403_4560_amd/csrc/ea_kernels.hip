@@ -1110,13 +1110,14 @@ constexpr int NOBS_VAL = 10;  // observables per slot (the count column aside)
 //     acc[j] / acc[0], kept normalized in LDS; D[j] = (rounded sum) / S.
 //  2. Observables of D: the central values.
 //  3. Replicate s: D_s[j] = (rounded exact sum less sample s's value) / (S-1),
-//     observables O_s; exact sums over s of O_s give the replicate mean
+//     observables O_s, kept in rep[t][s][10] (device memory of the caller:
+//     nT * S * 10 doubles); exact sums over s of O_s give the replicate mean
 //     Obar = (rounded sum) / S, then exact sums of (O_s - Obar)^2 give
-//     err = sqrt((S-1)/S * rounded sum).  Replicates are recomputed in the
-//     second pass (the same arithmetic), so nothing is stored per sample.
+//     err = sqrt((S-1)/S * rounded sum).  Each thread reads back only the
+//     replicates it wrote.
 __global__ void __launch_bounds__(256) finalize_kernel(const SampleDev *samples, const int32_t *sel, int S, int L,
-                                                       double two_sin, const double *acc, int jk, double *mean_out,
-                                                       double *err_out)
+                                                       double two_sin, const double *acc, int jk, double *rep,
+                                                       double *mean_out, double *err_out)
 {
     __shared__ uint32_t dig[NACC][XL];   // normalized digits of each column's exact sum
     __shared__ int32_t sgn[NACC];        // its final carry (0 or -1)
@@ -1158,23 +1159,30 @@ __global__ void __launch_bounds__(256) finalize_kernel(const SampleDev *samples,
         for (int i = tid; i < NOBS_VAL * 3; i += T) (&ospec[0][0])[i] = 0;
         __syncthreads();
         for (int i = tid; i < S; i += T) {
-            const double *a = acc + ((size_t)samples[sel[i]].slot_off + t) * NACC;
-            double Ds[NACC], o[NOBS_VAL];
-            for (int j = 0; j < NACC; ++j) {
-                const double m = a[j] / a[0];
-                const int c = exact_class(m);
-                const int n0 = spec[j][0] - (c == 0), n1 = spec[j][1] - (c == 1), n2 = spec[j][2] - (c == 2);
-                double v;
-                if (!exact_special(n0, n1, n2, &v)) {
-                    int64_t lim[XL];
-                    for (int k = 0; k < XL; ++k) lim[k] = (int64_t)dig[j][k];
-                    lim[XL - 1] += (int64_t)sgn[j] * ((int64_t)1 << 32);
-                    if (c < 0) exact_add(lim, m, true);
-                    v = exact_round(lim);
+            double *ro = rep + ((size_t)t * S + i) * NOBS_VAL;
+            double o[NOBS_VAL];
+            if (pass == 0) {
+                const double *a = acc + ((size_t)samples[sel[i]].slot_off + t) * NACC;
+                double Ds[NACC];
+                for (int j = 0; j < NACC; ++j) {
+                    const double m = a[j] / a[0];
+                    const int c = exact_class(m);
+                    const int n0 = spec[j][0] - (c == 0), n1 = spec[j][1] - (c == 1), n2 = spec[j][2] - (c == 2);
+                    double v;
+                    if (!exact_special(n0, n1, n2, &v)) {
+                        int64_t lim[XL];
+                        for (int k = 0; k < XL; ++k) lim[k] = (int64_t)dig[j][k];
+                        lim[XL - 1] += (int64_t)sgn[j] * ((int64_t)1 << 32);
+                        if (c < 0) exact_add(lim, m, true);
+                        v = exact_round(lim);
+                    }
+                    Ds[j] = v / (double)(S - 1);
                 }
-                Ds[j] = v / (double)(S - 1);
+                observables_of(Ds, L, two_sin, o);
+                for (int k = 0; k < NOBS_VAL; ++k) ro[k] = o[k];
+            } else {
+                for (int k = 0; k < NOBS_VAL; ++k) o[k] = ro[k];
             }
-            observables_of(Ds, L, two_sin, o);
             for (int k = 0; k < NOBS_VAL; ++k) {
                 double x = o[k];
                 if (pass == 1) {
