@@ -12,12 +12,18 @@ half-sweeps of every walker, 100 replica-exchange passes, 10 overlap
 measurements of every slot.  The metric is spin-flip attempts per ns
 (one attempt = one Metropolis trial at one site of one walker).
 
+The timed region replays each chunk from its captured hipGraph (the production
+path); an untimed pass of direct launches then records HIP events around the
+sweep kernels of every chunk for the roofline.
+
 Prints one JSON line (rank 0).  Besides the headline value it reports the
 unbatched form (the same kernels, one launch per sample, on a 64-sample subset,
 and, for L divisible by 8, the HBM-resident kernels that spread one sample's
-walkers over many workgroups, one sample per launch, on 16 samples),
-the roofline of the dominant kernel from HIP events recorded around each of
-its launches, and the CPU oracle on a bounded sample.
+walkers over many workgroups, one sample per launch, on 16 samples), the
+roofline of the dominant kernel (against the derived VALU peak and against the
+unit rates measured in-process, with its LDS traffic), the CPU oracle on a
+bounded sample (with the host's CPU model), and the same figures for the
+other workload shapes (L8_gauss, mixed_L6_12, L32_pm1) under other_workloads.
 """
 import argparse
 import json
@@ -84,8 +90,8 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # taken on; reported as null once the kernels change.
 MEASURED_TRAFFIC = {"L16_gauss": ("b11a8e83f689c066", 2.2589e9), "L32_pm1": ("b11a8e83f689c066", 3.5384e9)}
 KERNEL_SOURCES = tuple("paper_1403_4560_amd/csrc/" + f for f in (
-    "ea_kernels.hip", "ea_bits.hip", "ea_group.hip", "ea_item.hpp", "ea_update.hpp", "ea_device.hpp",
-    "ea_types.hpp"))
+    "ea_kernels.hip", "ea_bits.hip", "ea_group.hip", "ea_batch.hip", "ea_row.hpp", "ea_group.hpp", "ea_item.hpp",
+    "ea_update.hpp", "ea_device.hpp", "ea_types.hpp"))
 
 
 def kernel_fingerprint():
@@ -97,8 +103,49 @@ def kernel_fingerprint():
     return h.hexdigest()[:16]
 
 
+# Instruction mix of the algorithmic count per attempt, priced at the unit
+# rates measured on the device (ea_measure_peaks): 32x32->64 multiply-adds,
+# hardware exponentials and simple 32-bit operations.
+#   Gaussian, per 4-site word: Philox 18 multiply-adds; 4 exponentials; the
+#     other 93 operations simple (115 in all).
+#   +-1 one bit per spin, per 32-site word: 8 Philox calls = 144 multiply-adds,
+#     330.5 simple (474.5 in all).
+OP_MIX = {"gauss": {"mad": 18 / 4, "exp": 4 / 4, "simple": 93 / 4},
+          "bits": {"mad": 144 / 32, "exp": 0.0, "simple": 330.5 / 32}}
+# LDS bytes one attempt reads and writes by design (the dominant kernel):
+#   row engine, per 4-site word: 7 spin words (28 B), 6 coupling vectors of 4
+#     int32 (96 B) and on half the words one more coupling (2 B on average),
+#     the updated word (4 B): 130 B / 4;
+#   group engine, per site of a quad (4 attempts): own and 6 neighbour words
+#     (28 B), the neighbour table entry (16 B), 6 couplings (24 B), the store
+#     (4 B): 72 B / 4;
+#   one-bit engine, per 32-site word: own, 4 neighbour words and the x word
+#     (24 B), 6 bond words (24 B), 8 threshold reads per 8 sites, 3 spreading
+#     reads per 8 sites (44 B), the store (4 B): 96 B / 32.
+LDS_BYTES_PER_ATTEMPT = {"row": 130 / 4, "group": 72 / 4, "bits": 96 / 32}
+# LDS read bandwidth: 256 B per clock per CU on gfx950 (twice CDNA3's 128 B; the
+# measured 16-byte read rate, about 245 B per clock per CU, agrees)
+LDS_PEAK_TBPS = 256 * 256 * 2.4e9 / 1e12
+HBM_PEAK_TBPS = 8.0
+EXTRA_WORKLOADS = ("L8_gauss", "mixed_L6_12", "L32_pm1")
+ENGINE_OF = {"L16_gauss": "row", "L8_gauss": "row", "mixed_L6_12": "group", "L4_gauss": "group",
+             "L32_pm1": "bits"}
+
+
 def progress(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def cpu_baseline(work, n_samples, attempts):
@@ -113,8 +160,99 @@ def cpu_baseline(work, n_samples, attempts):
     dt = time.perf_counter() - t0
     attempts = sub.attempts_per_sweep() * sweeps
     return {"value": attempts / dt / 1e9, "unit": "attempts/ns", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": "%d of the %d samples x %d sweeps (%.3g attempts), %.1f s wall on %d threads"
                       % (n_samples, work.n_samples, sweeps, attempts, dt, threads)}
+
+
+def measured_peak_tops(mix, peaks):
+    """Lane-operations per second the kernel's instruction mix allows at the
+    measured unit rates (a harmonic mean weighted by the mix)."""
+    n = mix["mad"] + mix["exp"] + mix["simple"]
+    t = (mix["mad"] / peaks["valu_mad_u64_ops"] + mix["exp"] / peaks["valu_exp_ops"] +
+         mix["simple"] / peaks["valu_xor_ops"])
+    return n / t / 1e12
+
+
+def time_workload(binding, work, stream, steps, warmup, tier=0, timing_steps=3):
+    """Graph-replayed steps timed by the host clock (the production path), then
+    an untimed pass of direct launches with HIP events around the sweep
+    kernels of every chunk, for the roofline."""
+    import torch
+    ens = binding.Ensemble(work, stream=stream.cuda_stream, tier=tier)
+    ens.set_plan(chunk=SWEEPS_PER_STEP, use_graph=True)
+    for _ in range(warmup):
+        ens.sweep_pt(SWEEPS_PER_STEP)  # the first call captures the chunk's graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ens.sweep_pt(SWEEPS_PER_STEP)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ens.set_timing(True)
+    t1 = time.perf_counter()
+    for _ in range(timing_steps):
+        ens.sweep_pt(SWEEPS_PER_STEP)
+    torch.cuda.synchronize()
+    dt_direct = time.perf_counter() - t1
+    k_ms, k_launches = ens.kernel_time()
+    ens.set_timing(False)
+    bad = ens.check_energies()
+    engines = sorted(set(ens.engines()))
+    ens.close()
+    assert bad == 0, "incremental energies diverged"
+    return {"dt": dt, "ms_per_step": dt * 1e3 / steps, "direct_ms_per_step": dt_direct * 1e3 / timing_steps,
+            "avg_launch_s": k_ms / 1e3 / max(k_launches, 1), "engines": engines}
+
+
+def time_unbatched(binding, work, stream, n_samples, steps, tier=0):
+    import torch
+    sub = work.subset(range(min(n_samples, work.n_samples)))
+    ub = binding.Ensemble(sub, stream=stream.cuda_stream, tier=tier)
+    ub.set_plan(chunk=SWEEPS_PER_STEP)
+    ub.sweep_pt_unbatched(SWEEPS_PER_STEP)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        ub.sweep_pt_unbatched(SWEEPS_PER_STEP)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t1
+    ub.close()
+    return {"value": sub.attempts_per_sweep() * SWEEPS_PER_STEP * steps / (dt1 * 1e9), "unit": "attempts/ns",
+            "samples": sub.n_samples, "sweeps": SWEEPS_PER_STEP * steps}
+
+
+def roofline_of(name, work, timed, tier, peaks):
+    attempts_per_launch = work.attempts_per_sweep() * SWEEPS_PER_STEP  # one chunk per step
+    avg = timed["avg_launch_s"]
+    ops = ALG_OPS_PER_ATTEMPT[name]
+    if work.jkind == 1 and tier != 0:
+        ops = BYTE_PM1_OPS_PER_ATTEMPT  # +-1 couplings on the byte engines
+    fp, traffic = MEASURED_TRAFFIC.get(name, (None, None)) if tier == 0 else (None, None)
+    if fp != kernel_fingerprint():
+        traffic = None
+    kernel = KERNEL.get(name, "sweep kernels") if tier == 0 else "tier %d kernels" % tier
+    achieved = attempts_per_launch * ops / avg / 1e12
+    r = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+         "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+         "kernel": kernel, "avg_launch_ms": avg * 1e3,
+         "ops_per_attempt": ops, "traffic_unit": "HBM bytes per launch (hardware counters)"}
+    engine = ENGINE_OF.get(name, "group")
+    if tier == 0 and peaks is not None:
+        mp = measured_peak_tops(OP_MIX["bits" if engine == "bits" else "gauss"], peaks)
+        r["frac_measured_peaks"] = achieved / mp
+        r["measured_peak"] = mp
+    if tier == 0:
+        lb = LDS_BYTES_PER_ATTEMPT[engine]
+        lds = attempts_per_launch * lb / avg / 1e12
+        r["lds"] = {"bytes_per_attempt": lb, "achieved_TBps": lds, "peak_TBps": LDS_PEAK_TBPS,
+                    "frac": lds / LDS_PEAK_TBPS}
+        if peaks is not None:
+            r["lds"]["frac_measured_peak"] = lds / (peaks["lds_read_bytes"] / 1e12)
+    if traffic is not None:
+        hbm = traffic / avg / 1e12
+        r["hbm"] = {"achieved_TBps": hbm, "peak_TBps": HBM_PEAK_TBPS, "frac": hbm / HBM_PEAK_TBPS}
+    return r
 
 
 def main():
@@ -131,6 +269,9 @@ def main():
                     help="size of the CPU oracle sample (about 10-30 s of single-core work per 1e8)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-unbatched", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (L8_gauss, mixed_L6_12, L32_pm1) after the headline")
+    ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--autotune", action="store_true",
                     help="time candidate plans first (the L=16 row engine has no thread-count knob)")
     ap.add_argument("--tier", type=int, default=0,
@@ -142,6 +283,7 @@ def main():
     ap.add_argument("--peaks", action="store_true",
                     help="print the measured rates of the roofline's units (VALU issue of xor, 64-bit "
                          "multiply-add and high multiply; LDS read and HBM copy bandwidth) and exit")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the in-process unit-rate measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: every disorder sample is independent, so more GPUs "
@@ -154,8 +296,14 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    peaks = None
+    if args.peaks or not args.no_peaks:
+        peaks = binding.measure_peaks()
+        progress("measured unit rates: xor %.1f T, mad %.1f T, exp %.1f T lane-ops/s, LDS %.0f TB/s"
+                 % (peaks["valu_xor_ops"] / 1e12, peaks["valu_mad_u64_ops"] / 1e12, peaks["valu_exp_ops"] / 1e12,
+                    peaks["lds_read_bytes"] / 1e12))
     if args.peaks:
-        r = binding.measure_peaks()
+        r = peaks
         print(json.dumps({"peaks_measured": {
             "valu_xor_Tops": r["valu_xor_ops"] / 1e12, "valu_mad_u64_Tops": r["valu_mad_u64_ops"] / 1e12,
             "valu_mul_hi_Tops": r["valu_mul_hi_ops"] / 1e12, "lds_read_TBps": r["lds_read_bytes"] / 1e12,
@@ -170,63 +318,26 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     work = W.config_workload(args.workload, measure_start=0, measure_every=10)
-    ens = binding.Ensemble(work, stream=stream.cuda_stream, tier=args.tier)
-    ens.set_plan(chunk=SWEEPS_PER_STEP)
-    plan = ens.autotune(trial_sweeps=4) if args.autotune else ens.get_plan()
-    ens.set_plan(chunk=SWEEPS_PER_STEP)
+    plan_threads = 1024
+    if args.autotune:
+        with binding.Ensemble(work, stream=stream.cuda_stream, tier=args.tier) as ens:
+            ens.set_plan(chunk=SWEEPS_PER_STEP)
+            plan_threads = ens.autotune(trial_sweeps=4).threads
+    progress("workload %s ready" % args.workload)
     attempts_per_step = work.attempts_per_sweep() * SWEEPS_PER_STEP
-    progress("ensemble ready, plan threads=%d" % plan.threads)
-
-    for _ in range(args.warmup):
-        ens.sweep_pt(SWEEPS_PER_STEP)
-    ens.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ens.sweep_pt(SWEEPS_PER_STEP)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    k_ms, k_launches = ens.kernel_time()
-    ens.set_timing(False)
-    assert ens.check_energies() == 0, "incremental energies diverged"
+    timed = time_workload(binding, work, stream, args.steps, args.warmup, tier=args.tier)
+    dt = timed["dt"]
     value = attempts_per_step * args.steps / (dt * 1e9)
-    ens.close()
-    progress("timed %d steps in %.2f s: %.1f attempts/ns" % (args.steps, dt, value))
-
-    # roofline of the dominant kernel (the LDS-resident sweep kernel of the workload)
-    avg_launch_s = k_ms / 1e3 / max(k_launches, 1)
-    attempts_per_launch = attempts_per_step  # one launch per step (chunk)
-    ops = ALG_OPS_PER_ATTEMPT[args.workload]
-    if work.jkind == 1 and args.tier != 0:
-        ops = BYTE_PM1_OPS_PER_ATTEMPT  # +-1 couplings on the byte engines
-    fp, traffic = MEASURED_TRAFFIC.get(args.workload, (None, None)) if args.tier == 0 else (None, None)
-    if fp != kernel_fingerprint():
-        traffic = None
-    kernel = KERNEL.get(args.workload, "sweep kernels") if args.tier == 0 else "tier %d kernels" % args.tier
-    achieved = attempts_per_launch * ops / avg_launch_s / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                "kernel": kernel, "avg_launch_ms": avg_launch_s * 1e3,
-                "ops_per_attempt": ops, "traffic_unit": "HBM bytes per launch (hardware counters)"}
+    progress("timed %d graph-replayed steps in %.3f s: %.1f attempts/ns (direct launches: %.3f ms per step)"
+             % (args.steps, dt, value, timed["direct_ms_per_step"]))
+    roofline = roofline_of(args.workload, work, timed, args.tier, peaks)
 
     unbatched = None
     if not args.no_unbatched:
-        sub = work.subset(range(min(args.unbatched_samples, work.n_samples)))
-        ub = binding.Ensemble(sub, stream=stream.cuda_stream, tier=args.tier)
-        ub.set_plan(chunk=SWEEPS_PER_STEP, threads=plan.threads)
-        ub.sweep_pt_unbatched(SWEEPS_PER_STEP)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.unbatched_steps):
-            ub.sweep_pt_unbatched(SWEEPS_PER_STEP)
-        torch.cuda.synchronize()
-        dt1 = time.perf_counter() - t1
-        ub.close()
-        ub_value = sub.attempts_per_sweep() * SWEEPS_PER_STEP * args.unbatched_steps / (dt1 * 1e9)
-        progress("unbatched: %.1f attempts/ns" % ub_value)
-        unbatched = {"value": ub_value, "unit": "attempts/ns", "samples": sub.n_samples,
-                     "sweeps": SWEEPS_PER_STEP * args.unbatched_steps,
-                     "batched_over_unbatched": value / ub_value}
+        unbatched = time_unbatched(binding, work, stream, args.unbatched_samples, args.unbatched_steps,
+                                   tier=args.tier)
+        unbatched["batched_over_unbatched"] = value / unbatched["value"]
+        progress("unbatched: %.1f attempts/ns" % unbatched["value"])
         if all(int(L) % 8 == 0 for L in work.L):
             # the stronger one-sample-per-launch form: the HBM-resident kernels
             # spread one sample's walkers over many workgroups per launch
@@ -245,6 +356,23 @@ def main():
                                         "batched_over_spread": value / v2,
                                         "kernels": "HBM-resident half-sweep, exchange, snapshot per sweep"}
 
+    extra = None
+    if not args.no_extra and args.workload == "L16_gauss" and args.tier == 0:
+        extra = {}
+        for name in EXTRA_WORKLOADS:
+            w2 = W.config_workload(name, measure_start=0, measure_every=10)
+            t2 = time_workload(binding, w2, stream, args.extra_steps, 1)
+            v2 = w2.attempts_per_sweep() * SWEEPS_PER_STEP * args.extra_steps / (t2["dt"] * 1e9)
+            ub = time_unbatched(binding, w2, stream, 16, 1)
+            extra[name] = {"workload": WORKLOAD_TEXT[name], "value": v2, "unit": "attempts/ns",
+                           "steps": args.extra_steps, "ms_per_step": t2["ms_per_step"],
+                           "engines": t2["engines"],
+                           "roofline": roofline_of(name, w2, t2, 0, peaks),
+                           "unbatched": dict(ub, batched_over_unbatched=v2 / ub["value"])}
+            progress("%s: %.1f attempts/ns, frac %.3f, unbatched %.1f"
+                     % (name, v2, extra[name]["roofline"]["frac"], ub["value"]))
+            del w2
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(work, args.cpu_samples, args.cpu_attempts)
@@ -257,12 +385,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "sweeps_per_step": SWEEPS_PER_STEP, "samples": work.n_samples,
-                   "attempts_per_step": attempts_per_step, "threads_per_workgroup": plan.threads,
-                   "tier": args.tier,
+                   "attempts_per_step": attempts_per_step, "threads_per_workgroup": plan_threads,
+                   "tier": args.tier, "timed_path": "hipGraph replay of each 100-sweep chunk",
+                   "direct_launch_ms_per_step": timed["direct_ms_per_step"],
                    "parallelism": "samples x chains across workgroups"},
         "unbatched": unbatched,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "other_workloads": extra,
+        "peaks_measured": None if peaks is None else {
+            "valu_xor_Tops": peaks["valu_xor_ops"] / 1e12, "valu_mad_u64_Tops": peaks["valu_mad_u64_ops"] / 1e12,
+            "valu_exp_Tops": peaks["valu_exp_ops"] / 1e12, "lds_read_TBps": peaks["lds_read_bytes"] / 1e12,
+            "hbm_copy_TBps": peaks["hbm_copy_bytes"] / 1e12},
     }
     print(json.dumps(line), flush=True)
 

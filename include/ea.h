@@ -107,9 +107,16 @@ enum { EA_TIER_AUTO = 0, EA_TIER_HBM = 1, EA_TIER_BYTES = 2, EA_TIER_SITE = 3 };
 /* Launch plan.  Every plan gives bit-identical results. */
 typedef struct {
     int32_t chunk;      /* sweeps per persistent launch (>= 1)                  */
-    int32_t threads;    /* threads per workgroup: 256, 512 or 1024              */
+    int32_t threads;    /* threads per workgroup of the site engine's own
+                           launches: 256, 512 or 1024                           */
     int32_t use_graph;  /* 1: replay each chunk from a captured hipGraph       */
-    int32_t reserved;
+    int32_t batch;      /* 1: the lattice-size classes of the group, site and
+                           L = 8 row engines run as one persistent launch per
+                           chunk (a queue of units, longest first, each unit
+                           up to P items of one class run side by side by P
+                           teams of a workgroup; P per class is chosen by
+                           ea_autotune); 0: one launch per class.  Default 1
+                           when two or more such classes exist.             */
 } ea_plan;
 
 /* Create an ensemble from a description, copy it to the device and bind it
@@ -234,9 +241,33 @@ ea_status ea_set_plan(ea_ensemble *ens, const ea_plan *plan);
 ea_status ea_get_plan(const ea_ensemble *ens, ea_plan *plan);
 
 /* Time candidate plans on a copy of the state (the ensemble's state and
- * accumulators are restored afterwards) and keep the fastest.  Synchronizing.
- * trial_sweeps >= 1. */
+ * accumulators are restored afterwards) and keep the fastest: the teams per
+ * batch workgroup of every batch class (coordinate descent, class by class),
+ * the batch launch against one launch per class, and the workgroup size of
+ * the site engine's own launches.  If the environment variable EA_TUNE_CACHE
+ * names a file, a plan stored there under this ensemble's signature (device,
+ * coupling kind and launch classes) is applied without timing, and a newly
+ * tuned plan is stored.  The chunk length and graph use are left alone.
+ * Synchronizing.  trial_sweeps >= 1. */
 ea_status ea_autotune(ea_ensemble *ens, int32_t trial_sweeps);
+
+/* The layout of the batch launch (ea_plan.batch): one entry per launch class
+ * (a lattice size and engine, in launch order).  *n_classes receives the
+ * count; class_L, class_engine (ea_engine values) and teams [n_classes] may
+ * be NULL.  teams[c] = work items of class c that one batch workgroup runs
+ * side by side (1, 2, 4 or 8 teams of 512/teams threads), 0 for a class the
+ * batch launch does not take (one-bit, HBM-resident, and row-engine L = 16
+ * classes keep their own launches).  signature (17 bytes, may be NULL)
+ * receives the key under which ea_autotune caches this ensemble's plan. */
+ea_status ea_get_batch_plan(const ea_ensemble *ens, int32_t *n_classes, int32_t *class_L, int32_t *class_engine,
+                            int32_t *teams, char *signature);
+
+/* Set teams per batch workgroup for every class (layout as returned by
+ * ea_get_batch_plan; 0 for classes the batch launch does not take).
+ * EA_EINVAL if a value is not possible for its class (teams too small for the
+ * class's items, or their LDS frames beyond one workgroup's).  Results are
+ * unchanged; only the launch shape is.  Synchronizing. */
+ea_status ea_set_batch_plan(ea_ensemble *ens, const int32_t *teams);
 
 /* Kernel timing on the bound stream: when enabled, every sweep-kernel launch
  * is bracketed by HIP events; ea_kernel_time returns the summed duration in

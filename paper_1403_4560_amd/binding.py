@@ -48,7 +48,7 @@ class Desc(ctypes.Structure):
 
 class Plan(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("threads", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("batch", ctypes.c_int32)]
 
 
 _lib = None
@@ -71,6 +71,8 @@ _SIGS = [
     ("ea_set_plan", ctypes.c_int, [_VP, ctypes.POINTER(Plan)]),
     ("ea_get_plan", ctypes.c_int, [_VP, ctypes.POINTER(Plan)]),
     ("ea_autotune", ctypes.c_int, [_VP, _I32]),
+    ("ea_get_batch_plan", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    ("ea_set_batch_plan", ctypes.c_int, [_VP, _VP]),
     ("ea_set_timing", ctypes.c_int, [_VP, _I32]),
     ("ea_kernel_time", ctypes.c_int, [_VP, _VP, _VP]),
     ("ea_synchronize", ctypes.c_int, [_VP]),
@@ -306,8 +308,10 @@ class Ensemble:
         return {k: (m[:, i], e[:, i]) for i, k in enumerate(OBS_NAMES)}
 
     # -- planning and timing -------------------------------------------------
-    def set_plan(self, chunk=None, threads=None, use_graph=None):
+    def set_plan(self, chunk=None, threads=None, use_graph=None, batch=None):
         p = self.get_plan()
+        if batch is not None:
+            p.batch = int(bool(batch))
         if chunk is not None:
             p.chunk = int(chunk)
         if threads is not None:
@@ -320,6 +324,22 @@ class Ensemble:
         p = Plan()
         _check(load().ea_get_plan(self._h, ctypes.byref(p)))
         return p
+
+    def batch_plan(self) -> dict:
+        """Launch classes and teams per batch workgroup (0: own launch)."""
+        n = ctypes.c_int32()
+        _check(load().ea_get_batch_plan(self._h, ctypes.byref(n), None, None, None, None))
+        L = np.zeros(n.value, dtype=np.int32)
+        eng = np.zeros(n.value, dtype=np.int32)
+        teams = np.zeros(n.value, dtype=np.int32)
+        sig = ctypes.create_string_buffer(17)
+        _check(load().ea_get_batch_plan(self._h, ctypes.byref(n), _p(L), _p(eng), _p(teams), sig))
+        return {"L": L.tolist(), "engine": [ENGINE_NAMES[int(v)] for v in eng], "teams": teams.tolist(),
+                "signature": sig.value.decode()}
+
+    def set_batch_plan(self, teams):
+        t = np.ascontiguousarray(teams, dtype=np.int32)
+        _check(load().ea_set_batch_plan(self._h, _p(t)))
 
     def autotune(self, trial_sweeps: int = 4) -> Plan:
         _check(load().ea_autotune(self._h, int(trial_sweeps)))

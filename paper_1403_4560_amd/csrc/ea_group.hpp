@@ -1,0 +1,330 @@
+// ea_group.hpp -- walker-interleaved LDS engine for any even L <= 16 (both
+// coupling kinds): the lattice sizes that the row engine (Gaussian L = 8, 16)
+// and the one-bit engine (+-1 L = 8, 16, 32) do not take.
+//
+// Layout: one int8x4 word holds one site of four walkers of a chain (a
+// "quad"), [2 parities][quads][N/2 + 1 sites] (the odd plane stride spreads
+// the quads of a wave over all LDS banks); a per-item table gives every
+// sublattice site its six neighbours in the other sublattice as 16-bit
+// indices (both checkerboard offsets for x); a site's six neighbour words and
+// six bonds serve four Metropolis attempts at once and the neighbour
+// arithmetic works for any L (the four sites of a Philox group may lie in
+// different rows).  A work item is (quad, group of four consecutive sublattice
+// sites): four Philox calls, one per walker (counter (h >> 2, 2n + p,
+// (t << 1) | r, sample), word h & 3, as in every engine), then four word
+// updates.  Walkers beyond n_T in the last quad are padding: spins +1, never
+// flipped, never tallied.
+//
+// Device functions only: the per-class kernel (ea_group.hip) and the batch
+// kernel (ea_batch.hip) instantiate them.
+#pragma once
+
+#include "ea_device.hpp"
+#include "ea_item.hpp"
+#include "ea_types.hpp"
+#include "ea_update.hpp"
+
+namespace ea {
+
+// Neighbours of sublattice site (p, h) in the other sublattice, in the order
+// +x, -x, +y, -y, +z, -z.  Site bit k of row (y, z) sits at x = 2k + eps,
+// eps = (y + z + p) & 1.
+template <int L>
+__device__ __forceinline__ void group_nbrs(int p, int h, int nb[6])
+{
+    constexpr int HL = L / 2;
+    const int row = h / HL, k = h - row * HL;
+    const int y = row % L, z = row / L;
+    const int x = 2 * k + ((y + z + p) & 1);
+    const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
+    const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+    const int zp = z + 1 == L ? 0 : z + 1, zm = z == 0 ? L - 1 : z - 1;
+    nb[0] = (xp >> 1) + HL * row;
+    nb[1] = (xm >> 1) + HL * row;
+    nb[2] = k + HL * (yp + L * z);
+    nb[3] = k + HL * (ym + L * z);
+    nb[4] = k + HL * (y + L * zp);
+    nb[5] = k + HL * (y + L * zm);
+}
+
+// Word of (parity p, sublattice site h, quad q).
+template <int L>
+__device__ __forceinline__ int gidx(int p, int h, int q, int NQ)
+{
+    constexpr int PS = L * L * L / 2 + 1;
+    return (p * NQ + q) * PS + h;
+}
+
+// Neighbour table entry of sublattice site h: {+y | -y << 16, +z | -z << 16,
+// +x | -x << 16 for parity 0, the same for parity 1}.
+template <int L>
+__device__ __forceinline__ uint4 nbr_entry(int h)
+{
+    int n0[6], n1[6];
+    group_nbrs<L>(0, h, n0);
+    group_nbrs<L>(1, h, n1);
+    return make_uint4((uint32_t)n0[2] | (uint32_t)n0[3] << 16, (uint32_t)n0[4] | (uint32_t)n0[5] << 16,
+                      (uint32_t)n0[0] | (uint32_t)n0[1] << 16, (uint32_t)n1[0] | (uint32_t)n1[1] << 16);
+}
+
+struct GroupLane {
+    float cl[4];            // two_beta_log2e of each walker's slot
+    uint32_t c2[4];         // Philox counter word 2 of each walker
+    uint32_t thr[4];        // +-1: offset of each walker's threshold table in lut
+    uint32_t valid;         // 0xFF in the bytes of real walkers
+    float h32;              // the sample's field, held in a vector register
+};
+
+struct GroupTally {
+    uint32_t flips = 0;     // per byte: flipped sites of that walker
+    uint32_t fdown = 0;     // per byte: flipped sites that were -1
+    uint32_t nd = 0;        // per byte, second half: -1 spins after the update
+    int accE[4] = {0, 0, 0, 0};  // second half: sum of (S_u XOR m') per walker
+};
+
+// Metropolis update of work item (quad q, sites 4 g4 .. 4 g4 + 3) of parity P.
+template <int L, int JK, int P>
+__device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &d, uint32_t *SG, const void *Jl,
+                                           const uint32_t *lut, const float *b32, const uint4 *NB, int NQ, int q,
+                                           int g4, uint32_t c1, const GroupLane &ln, GroupTally &ty)
+{
+    constexpr int HALF = L * L * L / 2, PS = HALF + 1;
+    uint32_t *Sp = SG + (P * NQ + q) * PS;
+    const uint32_t *So = SG + ((1 - P) * NQ + q) * PS;
+    u32x4 rw[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rw[i] = philox4x32_10((uint32_t)g4, c1, ln.c2[i], d.sample_id, A.key0, A.key1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int h = 4 * g4 + k;
+        const uint4 te = NB[h];
+        const uint32_t tx = P ? te.w : te.z;
+        const int nb[6] = {(int)(tx & 0xFFFFu), (int)(tx >> 16), (int)(te.x & 0xFFFFu), (int)(te.x >> 16),
+                           (int)(te.y & 0xFFFFu), (int)(te.y >> 16)};
+        const uint32_t Sv = Sp[h];
+        uint32_t X[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) X[j] = So[nb[j]];
+        const u32x4 rk = {k == 0 ? rw[0].x : k == 1 ? rw[0].y : k == 2 ? rw[0].z : rw[0].w,
+                          k == 0 ? rw[1].x : k == 1 ? rw[1].y : k == 2 ? rw[1].z : rw[1].w,
+                          k == 0 ? rw[2].x : k == 1 ? rw[2].y : k == 2 ? rw[2].z : rw[2].w,
+                          k == 0 ? rw[3].x : k == 1 ? rw[3].y : k == 2 ? rw[3].z : rw[3].w};
+        uint32_t fm;
+        int Sus[4];
+        if constexpr (JK == 0) {
+            // bonds +x, -x, +y, -y, +z, -z: own +d bonds, the neighbours' +d bonds for -d
+            const int *Jp = (const int *)Jl + (size_t)P * 3 * HALF, *Jo = (const int *)Jl + (size_t)(1 - P) * 3 * HALF;
+            const int jx = Jp[h], jxm = Jo[nb[1]], jy = Jp[HALF + h], jym = Jo[HALF + nb[3]];
+            const int jz = Jp[2 * HALF + h], jzm = Jo[2 * HALF + nb[5]];
+            const int Ja[4] = {jx, jx, jx, jx}, Js[4] = {jxm, jxm, jxm, jxm};
+            const int Jy[4] = {jy, jy, jy, jy}, Jyn[4] = {jym, jym, jym, jym};
+            const int Jz[4] = {jz, jz, jz, jz}, Jzn[4] = {jzm, jzm, jzm, jzm};
+            // the exact path reads 2 beta32 of walker i's slot, t = bits 1 .. 27 of its counter word
+            fm = update_word_gauss<false>(Sv, X[0], X[1], X[2], X[3], X[4], X[5], Ja, Js, Jy, Jyn, Jz, Jzn, rk,
+                                          ln.cl, ln.cl, [&](int i) { return 2.0f * b32[(ln.c2[i] >> 1) & 0x7FFFFFFu]; },
+                                          ln.h32, 0, Sus) &
+                 ln.valid;
+        } else {
+            // bond-spin product bytes J s_j: 0x01 (+1) or 0xFF (-1); c counts the -1
+            const int8_t *Jp = (const int8_t *)Jl + (size_t)P * 3 * HALF;
+            const int8_t *Jo = (const int8_t *)Jl + (size_t)(1 - P) * 3 * HALF;
+            const int8_t jb[6] = {Jp[h], Jo[nb[1]], Jp[HALF + h], Jo[HALF + nb[3]], Jp[2 * HALF + h],
+                                  Jo[2 * HALF + nb[5]]};
+            constexpr uint32_t LOW = 0x01010101u;
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) cnt += ((X[j] ^ (jb[j] < 0 ? 0xFEFEFEFEu : 0u)) >> 7) & LOW;
+            const uint32_t words[4] = {rk.x, rk.y, rk.z, rk.w};
+            fm = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int sh = 8 * i;
+                const int b = 6 - (int)((cnt >> sh) & 0xFFu);               // (S_J + 6) / 2
+                const int m = __builtin_amdgcn_sbfe((int)Sv, sh + 7, 1);  // 0: s_i = +1, -1: s_i = -1
+                const int idx = (m + 1) * 7 + b;
+                Sus[i] = 2 * b - 6;  // S_J
+                const bool accept = ((d.down_mask >> idx) & 1u) | (words[i] < lut[ln.thr[i] + idx]);
+                fm |= accept ? 0xFEu << sh : 0u;
+            }
+            fm &= ln.valid;
+        }
+        Sp[h] = Sv ^ fm;
+        ty.flips += (fm >> 7) & 0x01010101u;
+        ty.fdown += ((fm & Sv) >> 7) & 0x01010101u;
+        if constexpr (P == 1) {
+            const uint32_t Sn = Sv ^ fm;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ty.accE[i] += Sus[i] ^ __builtin_amdgcn_sbfe((int)Sn, 8 * i + 7, 1);
+            ty.nd += (Sn >> 7) & 0x01010101u;
+        }
+    }
+}
+
+template <int L, int JK>
+__device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleDev &d, int r, char *smem,
+                                               const Team tm = whole_block())
+{
+    constexpr int N = L * L * L, HALF = N / 2, G4 = HALF / 4;
+    const int nT = d.n_T, NQ = (nT + 3) / 4;
+    const int T = tm.T, tid = tm.tid;
+    const GroupLdsOff o = group_lds_offsets(L, nT, JK);
+    uint32_t *SG = (uint32_t *)(smem + o.spins);
+    void *Jl = (void *)(smem + o.J);
+    uint32_t *lut = (uint32_t *)(smem + o.lut);
+    uint4 *NB = (uint4 *)(smem + o.nb);
+    ItemLds I{};
+    I.was = (int32_t *)(smem + o.was);
+    I.sow = (int32_t *)(smem + o.sow);
+    I.M = (int32_t *)(smem + o.M);
+    I.dM = (int32_t *)(smem + o.dM);
+    I.fl = (int32_t *)(smem + o.fl);
+    I.sw = (int32_t *)(smem + o.sw);
+    I.EJ = (long long *)(smem + o.EJ);
+    I.dEJ = (long long *)(smem + o.dEJ);
+    I.b32 = (float *)(smem + o.b32);
+    I.b64 = (double *)(smem + o.b64);
+
+    const size_t sbase = (size_t)d.spin_off + (size_t)r * nT * N;
+    const int gi = 2 * d.slot_off + r * nT;
+    // spins: int8 [walker][parity][N/2] -> quad words
+    for (int j = tid; j < 2 * HALF * NQ; j += T) {
+        const int q = j % NQ, ph = j / NQ;
+        uint32_t wv = 0;
+        for (int i = 0; i < 4; ++i) {
+            const int w = 4 * q + i;
+            const uint32_t b = w < nT ? (uint32_t)(uint8_t)A.spins[sbase + (size_t)w * N + ph] : 0x01u;
+            wv |= b << (8 * i);
+        }
+        SG[gidx<L>(ph / HALF, ph % HALF, q, NQ)] = wv;
+    }
+    for (int h = tid; h < HALF; h += T) NB[h] = nbr_entry<L>(h);
+    if constexpr (JK == 0) {
+        // couplings as exact int32 multiples of 2^-18
+        const float4 *src = (const float4 *)((const float *)A.J + d.J_off);  // J_off is a multiple of 4
+        int4 *dst = (int4 *)Jl;
+        for (int i = tid; i < 3 * N / 4; i += T) {
+            const float4 v = src[i];
+            dst[i] = make_int4((int)(v.x * 262144.0f), (int)(v.y * 262144.0f), (int)(v.z * 262144.0f),
+                               (int)(v.w * 262144.0f));
+        }
+    } else {
+        block_copy(Jl, (const int8_t *)A.J + d.J_off, (size_t)3 * N, tm);
+        for (int i = tid; i < nT * 14; i += T) lut[i] = A.lut[(size_t)d.slot_off * 14 + i];
+    }
+    for (int i = tid; i < nT; i += T) {
+        I.was[i] = A.was[gi + i];
+        I.sow[A.was[gi + i]] = i;  // kept by exchange_pass from here on
+        I.dEJ[i] = 0;
+        I.dM[i] = 0;
+        I.EJ[i] = A.EJ[gi + i];
+        I.M[i] = A.M[gi + i];
+        I.fl[i] = 0;
+        I.sw[i] = 0;
+        I.b32[i] = A.beta32[d.slot_off + i];
+        I.b64[i] = A.beta[d.slot_off + i];
+    }
+    __syncthreads();
+
+    // thread -> (quad, first site group); threads beyond NQ * TPQ stay idle
+    const int TPQ = T / NQ;
+    const int q = tid % NQ, gs = tid / NQ;
+    const bool on = gs < TPQ;
+    uint32_t valid = 0;
+    for (int i = 0; i < 4; ++i) valid |= (4 * q + i < nT ? 0xFFu : 0u) << (8 * i);
+    const double unit = JK == 0 ? 0x1p-18 : 1.0;
+    const double hd = (double)d.h32;
+    const int64_t n0 = A.state[0];
+    int64_t next_meas = next_measurement(n0, A.measure_every, A.measure_start);
+    int64_t f = 0;  // frame of the next measurement within this chunk
+    for (int it = 0; it < A.K; ++it) {
+        const int64_t n = n0 + it;
+        GroupLane ln;
+        int ts[4];
+        for (int i = 0; i < 4; ++i) {
+            const int w = 4 * q + i;
+            ts[i] = w < nT ? I.sow[w] : 0;
+            ln.cl[i] = two_beta_log2e(I.b32[ts[i]]);
+            ln.c2[i] = (PURPOSE_METROPOLIS << 28) | ((uint32_t)ts[i] << 1) | (uint32_t)r;
+            ln.thr[i] = 14 * ts[i];
+        }
+        ln.valid = valid;
+        ln.h32 = d.h32;
+        asm volatile("" : "+v"(ln.h32));
+        GroupTally ty;
+        if (on) {
+            const uint32_t c1 = (uint32_t)(2 * n);
+#pragma unroll 1
+            for (int g4 = gs; g4 < G4; g4 += TPQ)
+                group_item<L, JK, 0>(A, d, SG, Jl, lut, I.b32, NB, NQ, q, g4, c1, ln, ty);
+        }
+        __syncthreads();
+        if (on) {
+            const uint32_t c1 = (uint32_t)(2 * n + 1);
+#pragma unroll 1
+            for (int g4 = gs; g4 < G4; g4 += TPQ)
+                group_item<L, JK, 1>(A, d, SG, Jl, lut, I.b32, NB, NQ, q, g4, c1, ln, ty);
+            for (int i = 0; i < 4; ++i) {
+                const int w = 4 * q + i;
+                if (w >= nT) break;
+                const int fl = (int)((ty.flips >> (8 * i)) & 0xFFu), fd = (int)((ty.fdown >> (8 * i)) & 0xFFu);
+                const int nd = (int)((ty.nd >> (8 * i)) & 0xFFu);
+                // dEJ collects minus the new E_J (all threads of the quad add)
+                atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)((long long)ty.accE[i] + nd));
+                atomicAdd(&I.dM[w], -2 * (fl - 2 * fd));
+                atomicAdd(&I.fl[ts[i]], fl);
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < nT; i += T) {
+            I.EJ[i] = -I.dEJ[i];
+            I.M[i] += I.dM[i];
+            I.dEJ[i] = 0;  // cleared for the next sweep's tallies
+            I.dM[i] = 0;
+        }
+        __syncthreads();
+        exchange_pass(A, d, r, n, I, unit, hd, tm);
+        __syncthreads();
+        // Snapshot for the overlap measurement, in slot order.
+        const int64_t done = n + 1;
+        if (done == next_meas) {
+            next_meas += A.measure_every;
+            uint32_t *dst = A.frames + f * A.frame_words + d.frame_off + (size_t)r * nT * L * L;
+            for (int i = tid; !tm.ghost && i < nT * L * L; i += T) {
+                const int t = i / (L * L), row = i - t * (L * L);
+                const int w = I.was[t], wq = w >> 2, sh = 8 * (w & 3) + 7;
+                const int yz = (row % L) + row / L;
+                uint32_t bits = 0;
+                for (int x = 0; x < L; ++x) {
+                    const int p = (x + yz) & 1, h = (x + L * row) >> 1;
+                    bits |= ((SG[gidx<L>(p, h, wq, NQ)] >> sh) & 1u) << x;
+                }
+                dst[i] = bits;
+            }
+            for (int t = tid; !tm.ghost && t < nT; t += T) {
+                const int w = I.was[t];
+                A.frameE[f * 2 * A.total_slots + gi + t] = (double)I.EJ[w] * unit - hd * (double)I.M[w];
+            }
+            ++f;
+            __syncthreads();  // the next sweep changes the spins read here
+        }
+    }
+    __syncthreads();
+    for (int j = tid; !tm.ghost && j < 2 * HALF * NQ; j += T) {
+        const int q2 = j % NQ, ph = j / NQ;
+        const uint32_t wv = SG[gidx<L>(ph / HALF, ph % HALF, q2, NQ)];
+        for (int i = 0; i < 4; ++i) {
+            const int w = 4 * q2 + i;
+            if (w < nT) A.spins[sbase + (size_t)w * N + ph] = (int8_t)((wv >> (8 * i)) & 0xFFu);
+        }
+    }
+    for (int i = tid; !tm.ghost && i < nT; i += T) {
+        A.was[gi + i] = I.was[i];
+        A.EJ[gi + i] = I.EJ[i];
+        A.M[gi + i] = I.M[i];
+        A.flips[gi + i] += I.fl[i];
+        A.swaps[gi + i] += I.sw[i];
+    }
+    __syncthreads();
+}
+
+}  // namespace ea

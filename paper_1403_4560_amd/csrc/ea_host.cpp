@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -31,6 +32,8 @@ __global__ void hbm_exchange_kernel(SweepArgs A);
 __global__ void hbm_snapshot_kernel(SweepArgs A);
 template <int L> __global__ void measure_kernel(MeasureArgs A);
 __global__ void advance_kernel(int64_t *state, int64_t k);
+template <int JK> __global__ void batch_sweep_kernel(SweepArgs A, BatchArgs B);
+__global__ void batch_reset_kernel(int32_t *counter);
 __global__ void exp_bracket_kernel(uint32_t, uint32_t, unsigned long long *, unsigned int *);
 template <int JK>
 __global__ void energy_kernel(const SampleDev *, const int32_t *, const int8_t *, const void *, int64_t *,
@@ -136,6 +139,13 @@ struct ea_ensemble {
     std::vector<int32_t> sel_idx;   // [S] a finalize call's selection (no allocation per call)
     std::vector<char> sel_seen;     // [S]
     DevBuf jkrep;                   // jackknife replicates, grown on demand
+    // batch launch (ea_batch.hip) of the classes of the small LDS-resident engines
+    DevBuf batchbuf;                // queue counter (first 256 bytes), then the units
+    std::vector<int> class_P;       // per class: teams per batch workgroup, 0 = not batchable
+    int n_units = 0, batch_grid = 0;
+    size_t batch_lds = 0;
+    int cus = 0;                    // compute units of the device
+    size_t lds_per_cu = 0, lds_max = 0;
     void *static_scratch = nullptr; // this device's no-allocation scratch (0: not available)
     // launch classes: items sorted by lattice size, one launch per size
     struct Class {
@@ -295,7 +305,7 @@ void destroy_all(ea_ensemble *e)
                       &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->frames,
                       &e->frameE, &e->state, &e->slot_sample, &e->costab, &e->sintab,
                       &e->scratchE, &e->scratchM, &e->finout, &e->walkers, &e->dEJ, &e->dM,
-                      &e->sow, &e->Ju, &e->mslots, &e->Jbits, &e->sel, &e->jkrep};
+                      &e->sow, &e->Ju, &e->mslots, &e->Jbits, &e->sel, &e->jkrep, &e->batchbuf};
     for (DevBuf *b : bufs) dfree(*b);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
@@ -594,6 +604,95 @@ hipError_t launch_class(ea_ensemble *e, const ea_ensemble::Class &c, int K, int 
     return hipGetLastError();
 }
 
+// Batch launch.  A class is batchable if its engine is one the batch kernel
+// runs (group, site, or row at L = 8) and its items fit a team of at most
+// BATCH_THREADS threads.
+int batch_need(const ea_ensemble::Class &c)
+{
+    if (c.hbm || c.bits) return 0;
+    if (c.row) return c.L == 8 && c.threads <= BATCH_THREADS ? c.threads : 0;
+    if (c.group) return c.threads <= BATCH_THREADS ? c.threads : 0;
+    return 64;  // site engine: any team size
+}
+
+int batch_kind(const ea_ensemble::Class &c)
+{
+    return ((c.row ? BATCH_ROW : c.group ? BATCH_GROUP : BATCH_SITE) << 8) | c.L;
+}
+
+// The largest team count P in {1, 2, 4, 8} whose teams still hold need threads.
+int default_P(int need)
+{
+    int P = 1;
+    while (P < 8 && BATCH_THREADS / (2 * P) >= need) P *= 2;
+    return P;
+}
+
+bool batch_active(const ea_ensemble *e) { return e->plan.batch && e->n_units > 0; }
+
+// Units of every batchable class (class_P[c] teams per workgroup), queued
+// longest first, with the grid and LDS of the launch; uploaded to the device.
+ea_status build_batch(ea_ensemble *e)
+{
+    std::vector<std::pair<double, BatchUnit>> q;
+    size_t lds = 0;
+    for (size_t ci = 0; ci < e->classes.size(); ++ci) {
+        const auto &c = e->classes[ci];
+        const int P = e->class_P[ci];
+        if (P <= 0) continue;
+        const int T = BATCH_THREADS / P;
+        const size_t ldsc = (c.lds + 15) & ~(size_t)15;
+        lds = std::max(lds, P * ldsc);
+        int nTmax = 1;
+        for (int i = 0; i < c.count; i += 2) nTmax = std::max(nTmax, e->smp[e->sorted_samples[(c.begin + i) / 2]].nT);
+        const double factor = c.row ? 1.0 : c.group ? 1.25 : 2.0;  // relative time per attempt and thread
+        const double cost = (double)c.L * c.L * c.L * nTmax / T * factor;
+        for (int i = 0; i < c.count; i += P) {
+            BatchUnit u{};
+            u.kind = batch_kind(c);
+            u.first = c.begin + i;
+            u.count = std::min(P, c.count - i);
+            u.P = P;
+            u.lds = (int32_t)ldsc;
+            q.push_back({cost, u});
+        }
+    }
+    std::stable_sort(q.begin(), q.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    e->n_units = (int)q.size();
+    e->batch_lds = lds;
+    if (q.empty()) return EA_OK;
+    if ((size_t)e->n_units * sizeof(BatchUnit) + 256 > e->batchbuf.bytes)
+        return fail(EA_EINVAL, "internal error: %d batch units exceed the unit table", e->n_units);
+    const int wpc = (int)std::max<size_t>(1, std::min<size_t>(2, e->lds_per_cu / std::max<size_t>(lds, 1)));
+    e->batch_grid = std::min(e->n_units, e->cus * wpc);
+    std::vector<BatchUnit> units(q.size());
+    for (size_t i = 0; i < q.size(); ++i) units[i] = q[i].second;
+    HIP_TRY(e, hipMemcpyAsync((char *)e->batchbuf.p + 256, units.data(), sizeof(BatchUnit) * units.size(),
+                              hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    drop_graphs(e);  // captured graphs hold the old grid
+    return EA_OK;
+}
+
+hipError_t launch_batch(ea_ensemble *e, int K)
+{
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, e->stream, (int32_t *)e->batchbuf.p);
+    hipError_t st = hipGetLastError();
+    if (st != hipSuccess) return st;
+    SweepArgs A = sweep_args(e, K, (const int32_t *)e->items.p, 2 * e->S);
+    BatchArgs B{};
+    B.units = (const BatchUnit *)((const char *)e->batchbuf.p + 256);
+    B.n_units = e->n_units;
+    B.counter = (int32_t *)e->batchbuf.p;
+    if (e->jkind == EA_J_GAUSS_F32)
+        hipLaunchKernelGGL(batch_sweep_kernel<0>, dim3((unsigned)e->batch_grid), dim3(BATCH_THREADS), e->batch_lds,
+                           e->stream, A, B);
+    else
+        hipLaunchKernelGGL(batch_sweep_kernel<1>, dim3((unsigned)e->batch_grid), dim3(BATCH_THREADS), e->batch_lds,
+                           e->stream, A, B);
+    return hipGetLastError();
+}
+
 // One chunk: the sweep kernel(s), the measurement of the chunk's frames and
 // the advance of the device sweep counter.  unbatched: one launch per sample.
 hipError_t enqueue_chunk(ea_ensemble *e, int K, bool unbatched)
@@ -625,8 +724,13 @@ hipError_t enqueue_chunk(ea_ensemble *e, int K, bool unbatched)
             }
         }
     } else {
-        for (const auto &c : e->classes)
-            if (!c.hbm && (st = launch_class(e, c, K, c.begin, c.count, false)) != hipSuccess) return st;
+        const bool batch = batch_active(e);
+        if (batch && (st = launch_batch(e, K)) != hipSuccess) return st;
+        for (size_t ci = 0; ci < e->classes.size(); ++ci) {
+            const auto &c = e->classes[ci];
+            if (c.hbm || (batch && e->class_P[ci] > 0)) continue;
+            if ((st = launch_class(e, c, K, c.begin, c.count, false)) != hipSuccess) return st;
+        }
         for (int it = 0; it < K && e->any_hbm; ++it)
             for (const auto &c : e->classes)
                 if (c.hbm &&
@@ -706,7 +810,7 @@ ea_status plan_samples(const ea_desc *d, size_t lds_max, std::vector<SampleHost>
 // The persistent device buffers, in arena order (ea_bind_buffers), and their
 // sizes.  The snapshot frames (sized by the plan's chunk) and the scratch of
 // ea_check_energies stay outside.
-constexpr int NARENA = 26;
+constexpr int NARENA = 27;
 constexpr size_t ARENA_ALIGN = 256;
 
 void arena_buffers(ea_ensemble *e, DevBuf *b[NARENA])
@@ -714,7 +818,7 @@ void arena_buffers(ea_ensemble *e, DevBuf *b[NARENA])
     DevBuf *list[NARENA] = {&e->samples, &e->items, &e->spins, &e->J, &e->beta, &e->beta32, &e->lut,
                             &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->state,
                             &e->slot_sample, &e->costab, &e->sintab, &e->finout, &e->dEJ, &e->dM,
-                            &e->sow, &e->walkers, &e->Ju, &e->mslots, &e->Jbits, &e->sel};
+                            &e->sow, &e->walkers, &e->Ju, &e->mslots, &e->Jbits, &e->sel, &e->batchbuf};
     for (int k = 0; k < NARENA; ++k) b[k] = list[k];
 }
 
@@ -730,7 +834,7 @@ void arena_sizes(int S, int jkind, const SampleTotals &t, size_t sz[NARENA])
         sizeof(double) * (MAX_L + 1) * MAX_L, sizeof(double) * 2 * MAX_T * EA_NOBS, sizeof(int64_t) * 2 * TS,
         sizeof(int32_t) * 2 * TS, sizeof(int32_t) * 2 * TS, sizeof(int32_t) * (size_t)t.hbm_walkers,
         t.any_hbm && jkind == EA_J_GAUSS_F32 ? sizeof(int32_t) * (size_t)t.J_elems : 0, sizeof(int32_t) * TS,
-        sizeof(uint32_t) * (size_t)t.jbits_words, sizeof(int32_t) * S};
+        sizeof(uint32_t) * (size_t)t.jbits_words, sizeof(int32_t) * S, 256 + sizeof(BatchUnit) * 2 * (size_t)S};
     for (int k = 0; k < NARENA; ++k) sz[k] = sizes[k];
 }
 
@@ -859,6 +963,118 @@ ea_status run_finalize(ea_ensemble *e, const int32_t *sel, int32_t n, double *ou
     return EA_OK;
 }
 
+// Autotuner support.  Candidate team counts for batchable class ci: P in
+// {1, 2, 4, 8} with teams of at least the class's threads and P item frames
+// within one workgroup's LDS.
+std::vector<int> batch_candidates(const ea_ensemble *e, size_t ci)
+{
+    std::vector<int> out;
+    const auto &c = e->classes[ci];
+    const int need = batch_need(c);
+    const size_t ldsc = (c.lds + 15) & ~(size_t)15;
+    for (int P = 1; P <= 8; P *= 2)
+        if (need > 0 && BATCH_THREADS / P >= need && P * ldsc <= e->lds_max) out.push_back(P);
+    return out;
+}
+
+// A plan cache entry is keyed by what decides the launches: the device
+// architecture and compute units, the coupling kind and every class (engine,
+// L, items, largest n_T).
+std::string plan_signature(const ea_ensemble *e)
+{
+    hipDeviceProp_t prop{};
+    (void)hipGetDeviceProperties(&prop, e->device);
+    (void)hipGetLastError();
+    std::string k = std::string("ea-plan-v1;") + prop.gcnArchName + ";cu" + std::to_string(e->cus) + ";j" +
+                    std::to_string(e->jkind);
+    for (const auto &c : e->classes) {
+        int nTmax = 1;
+        for (int i = 0; i < c.count; i += 2) nTmax = std::max(nTmax, e->smp[e->sorted_samples[(c.begin + i) / 2]].nT);
+        k += ";" + std::to_string(c.hbm ? 4 : c.bits ? 3 : c.group ? 2 : c.row ? 1 : 0) + "/" + std::to_string(c.L) +
+             "/" + std::to_string(c.count) + "/" + std::to_string(nTmax);
+    }
+    uint64_t h = 1469598103934665603ull;  // FNV-1a
+    for (unsigned char ch : k) h = (h ^ ch) * 1099511628211ull;
+    char buf[32];
+    std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+    return buf;
+}
+
+struct TunedPlan {
+    int batch = 0, threads = 1024;
+    std::vector<int> P;
+};
+
+// Entry lines: "<signature> batch=<0|1> threads=<n> P=<p0>,<p1>,..." (one
+// value per class; 0 for classes the batch launch does not take).
+bool cache_lookup(const char *path, const std::string &sig, const ea_ensemble *e, TunedPlan &tp)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[4096];
+    bool found = false;
+    while (!found && std::fgets(line, sizeof line, f)) {
+        char key[64] = {0}, plist[3900] = {0};
+        int b = 0, t = 0;
+        if (std::sscanf(line, "%63s batch=%d threads=%d P=%3899s", key, &b, &t, plist) != 4 || sig != key) continue;
+        TunedPlan r;
+        r.batch = b;
+        r.threads = t;
+        for (char *tok = std::strtok(plist, ","); tok; tok = std::strtok(nullptr, ",")) r.P.push_back(std::atoi(tok));
+        if (r.P.size() != e->classes.size() || (b != 0 && b != 1) || (t != 256 && t != 512 && t != 1024)) continue;
+        bool ok = true;
+        for (size_t ci = 0; ci < r.P.size() && ok; ++ci) {
+            if (e->class_P[ci] <= 0) {
+                ok = r.P[ci] == 0;
+                continue;
+            }
+            const auto cand = batch_candidates(e, ci);
+            ok = std::find(cand.begin(), cand.end(), r.P[ci]) != cand.end();
+        }
+        if (ok) {
+            tp = r;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void apply_tuned(ea_ensemble *e, const TunedPlan &tp)
+{
+    e->plan.batch = tp.batch;
+    e->plan.threads = tp.threads;
+    for (size_t ci = 0; ci < tp.P.size(); ++ci)
+        if (e->class_P[ci] > 0) e->class_P[ci] = tp.P[ci];
+    drop_graphs(e);
+}
+
+// Rewrite the cache with this signature's entry replaced (other lines kept).
+void cache_store(const char *path, const std::string &sig, const ea_ensemble *e)
+{
+    std::vector<std::string> keep;
+    if (FILE *f = std::fopen(path, "r")) {
+        char line[4096];
+        while (std::fgets(line, sizeof line, f)) {
+            std::string l(line);
+            if (l.compare(0, sig.size(), sig) == 0 && l.size() > sig.size() && l[sig.size()] == ' ') continue;
+            keep.push_back(l);
+        }
+        std::fclose(f);
+    }
+    std::string entry = sig + " batch=" + std::to_string(e->plan.batch) + " threads=" +
+                        std::to_string(e->plan.threads) + " P=";
+    for (size_t ci = 0; ci < e->class_P.size(); ++ci)
+        entry += (ci ? "," : "") + std::to_string(std::max(e->class_P[ci], 0));
+    keep.push_back(entry + "\n");
+    const std::string tmp = std::string(path) + ".tmp";
+    if (FILE *f = std::fopen(tmp.c_str(), "w")) {
+        for (const auto &l : keep) std::fputs(l.c_str(), f);
+        std::fclose(f);
+        (void)std::rename(tmp.c_str(), path);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -881,6 +1097,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
     e->plan.chunk = 100;
     e->plan.threads = 1024;
     e->plan.use_graph = 1;
+    e->plan.batch = 1;
     if (hipGetDevice(&e->device) != hipSuccess) {
         delete e;
         return fail(EA_EDEVICE, "no HIP device");
@@ -958,6 +1175,30 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
             }
         }
         e->sorted_samples = order;
+        // batch launch: default teams per class; the batch kernel's LDS limit
+        int nb = 0;
+        for (const auto &c : e->classes) {
+            const int need = batch_need(c);
+            int P = need > 0 ? default_P(need) : 0;
+            const size_t ldsc = (c.lds + 15) & ~(size_t)15;
+            while (P > 1 && P * ldsc > lds_max) P /= 2;
+            if (P == 1 && ldsc > lds_max) P = 0;
+            e->class_P.push_back(P);
+            nb += P > 0;
+        }
+        if (nb < 2) e->plan.batch = 0;  // one class: its own launch is the same shape
+        for (int v = 0; v < 2; ++v)
+            (void)hipFuncSetAttribute(v ? (const void *)batch_sweep_kernel<1> : (const void *)batch_sweep_kernel<0>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+        int cus = 0, ldscu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, e->device) != hipSuccess) cus = 1;
+        if (hipDeviceGetAttribute(&ldscu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, e->device) !=
+            hipSuccess)
+            ldscu = (int)lds_max;
+        (void)hipGetLastError();
+        e->cus = std::max(cus, 1);
+        e->lds_per_cu = (size_t)std::max(ldscu, (int)lds_max);
+        e->lds_max = lds_max;
     }
 
     // host-side layouts
@@ -1098,7 +1339,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
             sizeof(int32_t) * was.size(), sz[8], sz[9], sz[10], sz[11], sz[12], sz[13],
             sizeof(int32_t) * slot_sample.size(), sizeof(double) * costab.size(), sizeof(double) * sintab.size(),
             sz[17], sz[18], sz[19], sz[20], sizeof(int32_t) * wtab.size(), sizeof(int32_t) * Ju.size(),
-            sizeof(int32_t) * mslots.size(), sizeof(uint32_t) * Jbits.size(), sz[25]};
+            sizeof(int32_t) * mslots.size(), sizeof(uint32_t) * Jbits.size(), sz[25], sz[26]};
         DevBuf *bufs[NARENA];
         arena_buffers(e, bufs);
         for (int k = 0; k < NARENA; ++k) {
@@ -1150,6 +1391,13 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
         hipMemsetAsync(e->dM.p, 0, e->dM.bytes, e->stream) != hipSuccess) {
         destroy_all(e);
         return fail(EA_EDEVICE, "memset failed");
+    }
+    {
+        ea_status bs = build_batch(e);
+        if (bs) {
+            destroy_all(e);
+            return bs;
+        }
     }
     // initial energies from scratch on the device
     if (e->jkind == EA_J_GAUSS_F32)
@@ -1372,7 +1620,8 @@ ea_status ea_set_plan(ea_ensemble *e, const ea_plan *p)
     for (const auto &h : e->smp)
         if ((int64_t)p->chunk * h.N >= ((int64_t)1 << 31))
             return fail(EA_EINVAL, "chunk too long for the per-chunk flip counters");
-    if (p->threads != e->plan.threads) drop_graphs(e);  // captured graphs embed the launch shape
+    if (p->batch != 0 && p->batch != 1) return fail(EA_EINVAL, "batch must be 0 or 1");
+    if (p->threads != e->plan.threads || p->batch != e->plan.batch) drop_graphs(e);  // graphs embed the launches
     e->plan = *p;
     return EA_OK;
 }
@@ -1417,6 +1666,13 @@ ea_status ea_autotune(ea_ensemble *e, int32_t trial_sweeps)
 {
     if (!usable(e)) return EA_ESTATE;
     if (trial_sweeps < 1) return fail(EA_EINVAL, "trial_sweeps must be >= 1");
+    const std::string sig = plan_signature(e);
+    const char *cache = std::getenv("EA_TUNE_CACHE");
+    TunedPlan tp;
+    if (cache && *cache && cache_lookup(cache, sig, e, tp)) {
+        apply_tuned(e, tp);
+        return build_batch(e);
+    }
     // back up the mutable state, time each candidate, restore
     DevBuf *mut[] = {&e->spins, &e->was, &e->EJ, &e->M, &e->flips, &e->swaps, &e->acc, &e->state, &e->sow};
     constexpr int NMUT = sizeof mut / sizeof mut[0];
@@ -1424,7 +1680,10 @@ ea_status ea_autotune(ea_ensemble *e, int32_t trial_sweeps)
     for (int i = 0; i < NMUT; ++i) {
         ea_status st = dalloc(e, bak[i], mut[i]->bytes);
         if (st) {
-            for (auto &b : bak) dfree(b);
+            for (auto &bb : bak) {
+                e->device_bytes -= (int64_t)bb.bytes;
+                dfree(bb);
+            }
             return st;
         }
         HIP_TRY(e, hipMemcpyAsync(bak[i].p, mut[i]->p, mut[i]->bytes, hipMemcpyDeviceToDevice, e->stream));
@@ -1433,44 +1692,148 @@ ea_status ea_autotune(ea_ensemble *e, int32_t trial_sweeps)
     const ea_plan orig = e->plan;
     const bool timing = e->timing;
     e->timing = false;
-    ea_plan best = orig;
-    double best_ms = 1e300;
-    const int cand[3] = {256, 512, 1024};
-    hipEvent_t a, b;
-    HIP_TRY(e, hipEventCreate(&a));
-    HIP_TRY(e, hipEventCreate(&b));
+    hipEvent_t ea, eb;
+    HIP_TRY(e, hipEventCreate(&ea));
+    HIP_TRY(e, hipEventCreate(&eb));
     ea_status result = EA_OK;
-    for (int c = 0; c < 3 && result == EA_OK; ++c) {
-        ea_plan p = orig;
-        p.threads = cand[c];
-        p.use_graph = 0;
+    // time of trial_sweeps sweeps under the current choices (best of two runs);
+    // the state is restored after each run
+    auto trial = [&](double *ms) -> ea_status {
+        ea_plan p = e->plan;
         p.chunk = trial_sweeps;
+        p.use_graph = 0;
+        const ea_plan keep = e->plan;
         e->plan = p;
-        HIP_TRY(e, hipEventRecord(a, e->stream));
-        result = run_sweeps(e, trial_sweeps, false);
-        HIP_TRY(e, hipEventRecord(b, e->stream));
-        HIP_TRY(e, hipEventSynchronize(b));
-        float ms = 0.f;
-        HIP_TRY(e, hipEventElapsedTime(&ms, a, b));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = orig;
-            best.threads = cand[c];
+        double best = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(e, hipEventRecord(ea, e->stream));
+            ea_status st = run_sweeps(e, trial_sweeps, false);
+            HIP_TRY(e, hipEventRecord(eb, e->stream));
+            HIP_TRY(e, hipEventSynchronize(eb));
+            float t = 0.f;
+            HIP_TRY(e, hipEventElapsedTime(&t, ea, eb));
+            for (int i = 0; i < NMUT; ++i)
+                HIP_TRY(e, hipMemcpyAsync(mut[i]->p, bak[i].p, mut[i]->bytes, hipMemcpyDeviceToDevice, e->stream));
+            e->sweep = sweep0;
+            if (st) {
+                e->plan = keep;
+                return st;
+            }
+            best = std::min(best, (double)t);
         }
-        for (int i = 0; i < NMUT; ++i)
-            HIP_TRY(e, hipMemcpyAsync(mut[i]->p, bak[i].p, mut[i]->bytes, hipMemcpyDeviceToDevice, e->stream));
-        e->sweep = sweep0;
+        e->plan = keep;
+        *ms = best;
+        return EA_OK;
+    };
+    double best_ms = 0.0;
+    result = trial(&best_ms);
+    // 1. teams per batch workgroup, class by class (coordinate descent), when
+    //    the batch launch is on
+    if (result == EA_OK && e->plan.batch && e->n_units > 0) {
+        for (size_t ci = 0; ci < e->classes.size() && result == EA_OK; ++ci) {
+            if (e->class_P[ci] <= 0) continue;
+            const int keepP = e->class_P[ci];
+            int bestP = keepP;
+            for (int P : batch_candidates(e, ci)) {
+                if (P == keepP) continue;
+                e->class_P[ci] = P;
+                if ((result = build_batch(e)) != EA_OK) break;
+                double ms = 0.0;
+                if ((result = trial(&ms)) != EA_OK) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    bestP = P;
+                }
+            }
+            e->class_P[ci] = bestP;
+            if (result == EA_OK) result = build_batch(e);
+        }
+    }
+    // 2. one batch launch against one launch per class
+    if (result == EA_OK && e->n_units > 0) {
+        e->plan.batch ^= 1;
+        double ms = 0.0;
+        result = trial(&ms);
+        if (result == EA_OK && ms < best_ms) best_ms = ms;
+        else e->plan.batch ^= 1;
+    }
+    // 3. workgroup size of the site engine's own launches
+    bool site_launch = false;
+    for (size_t ci = 0; ci < e->classes.size(); ++ci) {
+        const auto &c = e->classes[ci];
+        site_launch |= !c.hbm && !c.bits && !c.row && !c.group && !(e->plan.batch && e->class_P[ci] > 0);
+    }
+    if (result == EA_OK && site_launch) {
+        const int keepT = e->plan.threads;
+        int bestT = keepT;
+        for (int T : {256, 512, 1024}) {
+            if (T == keepT) continue;
+            e->plan.threads = T;
+            double ms = 0.0;
+            if ((result = trial(&ms)) != EA_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                bestT = T;
+            }
+        }
+        e->plan.threads = bestT;
     }
     HIP_TRY(e, hipStreamSynchronize(e->stream));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
     for (auto &bb : bak) {
         e->device_bytes -= (int64_t)bb.bytes;
         dfree(bb);
     }
     e->timing = timing;
-    e->plan = best;
+    const ea_plan tuned = e->plan;
+    e->plan = orig;
+    e->plan.threads = tuned.threads;
+    e->plan.batch = tuned.batch;
+    drop_graphs(e);
+    if (result == EA_OK) result = build_batch(e);
+    if (result == EA_OK && cache && *cache) cache_store(cache, sig, e);
     return result;
+}
+
+ea_status ea_get_batch_plan(const ea_ensemble *e, int32_t *n_classes, int32_t *class_L, int32_t *class_engine,
+                            int32_t *teams, char *signature)
+{
+    if (!e || !n_classes) return fail(EA_EINVAL, "null argument");
+    *n_classes = (int32_t)e->classes.size();
+    for (size_t ci = 0; ci < e->classes.size(); ++ci) {
+        const auto &c = e->classes[ci];
+        if (class_L) class_L[ci] = c.L;
+        if (class_engine)
+            class_engine[ci] = c.hbm ? EA_ENGINE_HBM : c.bits ? EA_ENGINE_BITS : c.group ? EA_ENGINE_GROUP
+                               : c.row ? EA_ENGINE_ROW : EA_ENGINE_SITE;
+        if (teams) teams[ci] = std::max(e->class_P[ci], 0);
+    }
+    if (signature) {
+        const std::string sig = plan_signature(e);
+        std::memcpy(signature, sig.c_str(), sig.size() + 1);
+    }
+    return EA_OK;
+}
+
+ea_status ea_set_batch_plan(ea_ensemble *e, const int32_t *teams)
+{
+    if (!usable(e)) return EA_ESTATE;
+    if (!teams) return fail(EA_EINVAL, "teams is NULL");
+    for (size_t ci = 0; ci < e->classes.size(); ++ci) {
+        if (e->class_P[ci] <= 0) {
+            if (teams[ci] != 0) return fail(EA_EINVAL, "class %zu is not run by the batch launch; give 0", ci);
+            continue;
+        }
+        const auto cand = batch_candidates(e, ci);
+        if (std::find(cand.begin(), cand.end(), teams[ci]) == cand.end())
+            return fail(EA_EINVAL, "class %zu (L=%d): %d teams per workgroup is not possible", ci, e->classes[ci].L,
+                        teams[ci]);
+    }
+    HIP_TRY(e, hipStreamSynchronize(e->stream));
+    for (size_t ci = 0; ci < e->classes.size(); ++ci)
+        if (e->class_P[ci] > 0) e->class_P[ci] = teams[ci];
+    return build_batch(e);
 }
 
 ea_status ea_synchronize(ea_ensemble *e)

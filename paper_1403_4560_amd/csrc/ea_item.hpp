@@ -8,11 +8,25 @@
 
 namespace ea {
 
-// Block-cooperative byte copy, 16 bytes at a time when both ends allow it;
+// The threads that run one work item: the whole workgroup, or one of the
+// equal, wave-aligned teams a batch workgroup is split into (each team with
+// its own LDS region; every team passes the same barriers).  A ghost team
+// computes like a real one on a copy of a real item but writes nothing to
+// global memory (it fills a batch unit that has fewer items than teams).
+struct Team {
+    int tid;     // thread index within the team
+    int T;       // threads in the team
+    bool ghost;
+};
+
+__device__ __forceinline__ Team whole_block() { return Team{(int)threadIdx.x, (int)blockDim.x, false}; }
+
+// Team-cooperative byte copy, 16 bytes at a time when both ends allow it;
 // four copies in flight per thread.
-__device__ __forceinline__ void block_copy(void *__restrict__ dst, const void *__restrict__ src, size_t bytes)
+__device__ __forceinline__ void block_copy(void *__restrict__ dst, const void *__restrict__ src, size_t bytes,
+                                           const Team tm = whole_block())
 {
-    const int T = blockDim.x, tid = threadIdx.x;
+    const int T = tm.T, tid = tm.tid;
     if ((((uintptr_t)dst | (uintptr_t)src | bytes) & 15) == 0) {
         int4 *__restrict__ d = (int4 *)dst;
         const int4 *__restrict__ s = (const int4 *)src;
@@ -36,9 +50,9 @@ __device__ __forceinline__ void block_copy(void *__restrict__ dst, const void *_
 // count walkers of bytes each (a multiple of 8) from consecutive blocks at
 // glob to blocks lstride bytes apart at lds (to_lds), or back, in 8-byte words.
 __device__ __forceinline__ void copy_walkers(int8_t *lds, size_t lstride, int8_t *glob, int count, size_t bytes,
-                                             bool to_lds)
+                                             bool to_lds, const Team tm = whole_block())
 {
-    const int T = blockDim.x, tid = threadIdx.x;
+    const int T = tm.T, tid = tm.tid;
     const size_t per = bytes / 8, total = per * (size_t)count;
     for (size_t i = tid; i < total; i += T) {
         const size_t w = i / per, j = i - w * per;
@@ -143,10 +157,10 @@ __device__ __forceinline__ ItemLds item_lds(char *smem, int L, int nT, int jkind
 // both maps (was: slot -> walker, sow: walker -> slot), so the sweep that
 // follows reads its temperatures without rebuilding sow.
 __device__ __forceinline__ void exchange_pass(const SweepArgs &A, const SampleDev &d, int r, int64_t n,
-                                              const ItemLds &I, double unit, double hd)
+                                              const ItemLds &I, double unit, double hd, const Team tm = whole_block())
 {
-    const int nT = d.n_T, T = blockDim.x;
-    for (int j = threadIdx.x;; j += T) {
+    const int nT = d.n_T, T = tm.T;
+    for (int j = tm.tid;; j += T) {
         const int t = (int)(n & 1) + 2 * j;
         if (t + 1 >= nT) break;
         const int w0 = I.was[t], w1 = I.was[t + 1];

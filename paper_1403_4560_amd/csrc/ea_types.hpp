@@ -109,6 +109,30 @@ struct MeasureArgs {
     int64_t measure_start;
 };
 
+// Batch launch (ea_batch.hip): one persistent launch runs the work items of
+// every lattice-size class of the small LDS-resident engines.  A unit is up to
+// P items of one class that P equal, wave-aligned teams of a workgroup run
+// side by side; workgroups take units from a queue ordered by decreasing cost
+// (longest first), so no class waits for another's tail.
+enum { BATCH_SITE = 0, BATCH_ROW = 1, BATCH_GROUP = 2 };
+constexpr int BATCH_THREADS = 512;
+
+struct BatchUnit {
+    int32_t kind;   // engine << 8 | L
+    int32_t first;  // index of the unit's first item in the item list
+    int32_t count;  // real items, 1 .. P; teams beyond count run ghosts
+    int32_t P;      // teams (threads per team: BATCH_THREADS / P)
+    int32_t lds;    // LDS bytes per team (a multiple of 16)
+    int32_t pad[3];
+};
+
+struct BatchArgs {
+    const BatchUnit *units;
+    int32_t n_units;
+    int32_t pad;
+    int32_t *counter;  // next unit of the queue; zeroed before every launch
+};
+
 // Number of measurement sweeps among completed-sweep counts 1..x.
 __host__ __device__ inline int64_t measurements_upto(int64_t x, int32_t m, int64_t start)
 {

@@ -400,6 +400,45 @@ def test_full_L16_workload_sampled(torch_cuda):
     assert_same(work, st, ms, ref, samples=pick)
 
 
+def test_full_L8_workload_sampled(torch_cuda):
+    """The whole 1024-sample, 16-temperature L = 8 batch in the benchmark's
+    plan (graph replay), measuring from the first sweep; three samples spread
+    over the batch compared one by one against the oracle."""
+    from paper_1403_4560_amd import binding
+    work = W.config_workload("L8_gauss", measure_start=0)
+    sweeps = 20
+    print("case: full L8 batch, 1024 samples, %d sweeps" % sweeps, flush=True)
+    with binding.Ensemble(work) as ens:
+        ens.set_plan(chunk=10)
+        ens.sweep_pt(sweeps)
+        st = ens.read_state()
+        ms = ens.measure()
+        assert ens.check_energies() == 0
+    pick = [0, 511, 1023]
+    ref = O.OracleEnsemble(work.subset(pick)).run(sweeps)
+    assert_same(work, st, ms, ref, samples=pick)
+
+
+def test_full_mixed_workload_sampled(torch_cuda):
+    """The whole 4096-sample mixed batch (L = 6, 8, 10, 12; h = 0.1, 0.2,
+    0.3), measuring from the first sweep; two samples of every lattice size at
+    two different fields, from both ends of the batch, against the oracle."""
+    from paper_1403_4560_amd import binding
+    work = W.config_workload("mixed_L6_12", measure_start=0)
+    sweeps = 20
+    print("case: full mixed batch, 4096 samples, %d sweeps" % sweeps, flush=True)
+    with binding.Ensemble(work) as ens:
+        ens.set_plan(chunk=10)
+        ens.sweep_pt(sweeps)
+        st = ens.read_state()
+        ms = ens.measure()
+        assert ens.check_energies() == 0
+    pick = [0, 4, 9, 13, 4094, 4087, 4092, 4091, 2050]
+    assert len({(int(work.L[s]), float(work.h[s])) for s in pick}) == 8
+    ref = O.OracleEnsemble(work.subset(pick)).run(sweeps)
+    assert_same(work, st, ms, ref, samples=pick)
+
+
 def test_L16_long_run_in_the_bench_plan(torch_cuda):
     """Two L = 16 samples for 600 sweeps in the benchmark's plan (chunks of 100
     replayed from a hipGraph), measuring every 10 sweeps from 300: spins,
@@ -433,18 +472,105 @@ def test_fast_exponential_bracket_is_exhaustively_safe(torch_cuda):
     assert dev < 2.0 ** -13
 
 
-def test_autotune_keeps_results(torch_cuda):
+def test_autotune_keeps_results(torch_cuda, monkeypatch):
     from paper_1403_4560_amd import binding
+    monkeypatch.delenv("EA_TUNE_CACHE", raising=False)
     work = W.config_workload("mixed_L6_12", samples=[0, 1, 2, 3], measure_start=0)
     with binding.Ensemble(work) as ens:
         ens.sweep_pt(7)
         plan = ens.autotune(trial_sweeps=3)
-        assert plan.threads in (256, 512, 1024)
+        assert plan.threads in (256, 512, 1024) and plan.batch in (0, 1)
         ens.sweep_pt(13)
         st = ens.read_state()
         ms = ens.measure()
     ref = O.OracleEnsemble(work).run(20)
     assert_same(work, st, ms, ref)
+
+
+# --- the batch launch: every lattice-size class of the small engines in one
+# persistent launch, units of up to P items per workgroup --------------------
+def batch_variants(ens):
+    """Team plans to try: the default, and the largest and the smallest
+    possible teams per workgroup for every batch class."""
+    from paper_1403_4560_amd import binding
+    base = list(ens.batch_plan()["teams"])
+    cands = []
+    for i, p in enumerate(base):
+        if p == 0:
+            cands.append([0])
+            continue
+        ok = []
+        for P in (1, 2, 4, 8):
+            t = list(base)
+            t[i] = P
+            try:
+                ens.set_batch_plan(t)
+                ok.append(P)
+            except binding.EAError:
+                pass
+        cands.append(ok)
+    ens.set_batch_plan(base)
+    return [base, [max(c) for c in cands], [min(c) for c in cands]]
+
+
+@pytest.mark.parametrize("jkind", [W.J_GAUSS, W.J_PM1])
+def test_batch_launch_plans_match_oracle(torch_cuda, jkind):
+    """Uneven sizes and ladder lengths (group engine at L = 6, 10, 12, row
+    engine at L = 8 for Gaussian couplings, site engine at L = 4), as one batch
+    launch with several team plans (ghost teams included) and as one launch
+    per class: every plan equals the oracle bit for bit."""
+    from paper_1403_4560_amd import binding
+    Ls = [6, 8, 10, 12, 4, 6, 8, 12, 10, 6, 4, 6, 6]
+    nT = [16, 16, 16, 16, 8, 5, 13, 16, 7, 16, 3, 16, 16]
+    hs = [0.1, 0.2, 0.3, 0.1, 0.2, 0.3, 0.1, 0.2, 0.3, 0.1, 0.2, 0.3, 0.0]
+    work = W.make_workload(Ls, nT, (0.5, 1.6), hs, jkind=jkind, measure_every=4, measure_start=4,
+                           name="batch plans")
+    sweeps = 18
+    ref = O.OracleEnsemble(work).run(sweeps)
+    with binding.Ensemble(work) as ens:
+        assert ens.get_plan().batch == 1
+        variants = batch_variants(ens)
+    assert any(v != variants[0] for v in variants[1:])
+    for teams in variants + [None]:
+        print("case: batch plan", teams, "jkind", jkind, flush=True)
+        with binding.Ensemble(work) as ens:
+            if teams is None:
+                ens.set_plan(batch=False)
+            else:
+                ens.set_batch_plan(teams)
+            ens.set_plan(chunk=7)
+            ens.sweep_pt(sweeps)
+            st = ens.read_state()
+            ms = ens.measure()
+            assert ens.check_energies() == 0
+        assert_same(work, st, ms, ref)
+
+
+def test_autotune_plan_cache(torch_cuda, tmp_path, monkeypatch):
+    """The autotuner stores its plan under the ensemble's signature and a
+    second ensemble of the same shape takes it from the cache; results are
+    unchanged."""
+    from paper_1403_4560_amd import binding
+    cache = tmp_path / "plans.txt"
+    monkeypatch.setenv("EA_TUNE_CACHE", str(cache))
+    work = W.config_workload("mixed_L6_12", samples=range(16), measure_start=0)
+    with binding.Ensemble(work) as ens:
+        ens.sweep_pt(5)
+        p1 = ens.autotune(trial_sweeps=2)
+        b1 = ens.batch_plan()
+        ens.sweep_pt(9)
+        st = ens.read_state()
+        ms = ens.measure()
+    text = cache.read_text()
+    assert text.startswith(b1["signature"] + " batch=%d threads=%d P=" % (p1.batch, p1.threads))
+    ref = O.OracleEnsemble(work).run(14)
+    assert_same(work, st, ms, ref)
+    with binding.Ensemble(work) as ens2:
+        other = [0 if t == 0 else 1 for t in b1["teams"]]
+        ens2.set_batch_plan(other)
+        p2 = ens2.autotune(trial_sweeps=2)      # from the cache: no timing
+        assert ens2.batch_plan()["teams"] == b1["teams"] and p2.batch == p1.batch
+    assert cache.read_text() == text
 
 
 # --- multispin (one bit per spin) engine, +-1 couplings at L = 8, 16, 32 -------
