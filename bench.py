@@ -174,13 +174,16 @@ def measured_peak_tops(mix, peaks):
     return n / t / 1e12
 
 
-def time_workload(binding, work, stream, steps, warmup, tier=0, timing_steps=3):
+def time_workload(binding, work, stream, steps, warmup, tier=0, timing_steps=3, autotune=True):
     """Graph-replayed steps timed by the host clock (the production path), then
     an untimed pass of direct launches with HIP events around the sweep
-    kernels of every chunk, for the roofline."""
+    kernels of every chunk, for the roofline.  The plan is autotuned first
+    (outside the timed region)."""
     import torch
     ens = binding.Ensemble(work, stream=stream.cuda_stream, tier=tier)
+    plan = ens.autotune(trial_sweeps=4) if autotune else ens.get_plan()
     ens.set_plan(chunk=SWEEPS_PER_STEP, use_graph=True)
+    bplan = ens.batch_plan()
     for _ in range(warmup):
         ens.sweep_pt(SWEEPS_PER_STEP)  # the first call captures the chunk's graph
     torch.cuda.synchronize()
@@ -202,7 +205,10 @@ def time_workload(binding, work, stream, steps, warmup, tier=0, timing_steps=3):
     ens.close()
     assert bad == 0, "incremental energies diverged"
     return {"dt": dt, "ms_per_step": dt * 1e3 / steps, "direct_ms_per_step": dt_direct * 1e3 / timing_steps,
-            "avg_launch_s": k_ms / 1e3 / max(k_launches, 1), "engines": engines}
+            "avg_launch_s": k_ms / 1e3 / max(k_launches, 1), "engines": engines,
+            "plan": {"batch_launch": bool(plan.batch), "site_threads": plan.threads,
+                     "classes": [{"L": L, "engine": e, "items_per_workgroup": t}
+                                 for L, e, t in zip(bplan["L"], bplan["engine"], bplan["teams"])]}}
 
 
 def time_unbatched(binding, work, stream, n_samples, steps, tier=0):
@@ -272,8 +278,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (L8_gauss, mixed_L6_12, L32_pm1) after the headline")
     ap.add_argument("--extra-steps", type=int, default=5)
-    ap.add_argument("--autotune", action="store_true",
-                    help="time candidate plans first (the L=16 row engine has no thread-count knob)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the plan autotuning done before each timed workload")
     ap.add_argument("--tier", type=int, default=0,
                     help="0 automatic (default); 1 HBM-resident for L divisible by 8; 2 no one-bit engine; "
                          "3 one-site-per-thread engine (comparisons only)")
@@ -318,14 +324,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     work = W.config_workload(args.workload, measure_start=0, measure_every=10)
-    plan_threads = 1024
-    if args.autotune:
-        with binding.Ensemble(work, stream=stream.cuda_stream, tier=args.tier) as ens:
-            ens.set_plan(chunk=SWEEPS_PER_STEP)
-            plan_threads = ens.autotune(trial_sweeps=4).threads
     progress("workload %s ready" % args.workload)
     attempts_per_step = work.attempts_per_sweep() * SWEEPS_PER_STEP
-    timed = time_workload(binding, work, stream, args.steps, args.warmup, tier=args.tier)
+    timed = time_workload(binding, work, stream, args.steps, args.warmup, tier=args.tier,
+                          autotune=not args.no_autotune)
     dt = timed["dt"]
     value = attempts_per_step * args.steps / (dt * 1e9)
     progress("timed %d graph-replayed steps in %.3f s: %.1f attempts/ns (direct launches: %.3f ms per step)"
@@ -361,12 +363,12 @@ def main():
         extra = {}
         for name in EXTRA_WORKLOADS:
             w2 = W.config_workload(name, measure_start=0, measure_every=10)
-            t2 = time_workload(binding, w2, stream, args.extra_steps, 1)
+            t2 = time_workload(binding, w2, stream, args.extra_steps, 1, autotune=not args.no_autotune)
             v2 = w2.attempts_per_sweep() * SWEEPS_PER_STEP * args.extra_steps / (t2["dt"] * 1e9)
             ub = time_unbatched(binding, w2, stream, 16, 1)
             extra[name] = {"workload": WORKLOAD_TEXT[name], "value": v2, "unit": "attempts/ns",
                            "steps": args.extra_steps, "ms_per_step": t2["ms_per_step"],
-                           "engines": t2["engines"],
+                           "engines": t2["engines"], "plan": t2["plan"],
                            "roofline": roofline_of(name, w2, t2, 0, peaks),
                            "unbatched": dict(ub, batched_over_unbatched=v2 / ub["value"])}
             progress("%s: %.1f attempts/ns, frac %.3f, unbatched %.1f"
@@ -385,7 +387,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "sweeps_per_step": SWEEPS_PER_STEP, "samples": work.n_samples,
-                   "attempts_per_step": attempts_per_step, "threads_per_workgroup": plan_threads,
+                   "attempts_per_step": attempts_per_step, "plan": timed["plan"],
                    "tier": args.tier, "timed_path": "hipGraph replay of each 100-sweep chunk",
                    "direct_launch_ms_per_step": timed["direct_ms_per_step"],
                    "parallelism": "samples x chains across workgroups"},

@@ -55,16 +55,21 @@ __device__ __forceinline__ int gidx(int p, int h, int q, int NQ)
     return (p * NQ + q) * PS + h;
 }
 
-// Neighbour table entry of sublattice site h: {+y | -y << 16, +z | -z << 16,
-// +x | -x << 16 for parity 0, the same for parity 1}.
+// Neighbour table entry of sublattice site h: the byte offsets 4 n of its
+// neighbour words (and of their int32 bonds) in 16-bit halves, {+y | -y << 16,
+// +z | -z << 16, +x | -x << 16 for parity 0, the same for parity 1}, so that
+// an address is one add of a half-word to a base (4 n < 2^16 for L <= 16).
 template <int L>
 __device__ __forceinline__ uint4 nbr_entry(int h)
 {
+    static_assert(2 * L * L * L < 65536, "byte offsets must fit 16 bits");
     int n0[6], n1[6];
     group_nbrs<L>(0, h, n0);
     group_nbrs<L>(1, h, n1);
-    return make_uint4((uint32_t)n0[2] | (uint32_t)n0[3] << 16, (uint32_t)n0[4] | (uint32_t)n0[5] << 16,
-                      (uint32_t)n0[0] | (uint32_t)n0[1] << 16, (uint32_t)n1[0] | (uint32_t)n1[1] << 16);
+    return make_uint4((uint32_t)(4 * n0[2]) | (uint32_t)(4 * n0[3]) << 16,
+                      (uint32_t)(4 * n0[4]) | (uint32_t)(4 * n0[5]) << 16,
+                      (uint32_t)(4 * n0[0]) | (uint32_t)(4 * n0[1]) << 16,
+                      (uint32_t)(4 * n1[0]) | (uint32_t)(4 * n1[1]) << 16);
 }
 
 struct GroupLane {
@@ -99,12 +104,11 @@ __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &
         const int h = 4 * g4 + k;
         const uint4 te = NB[h];
         const uint32_t tx = P ? te.w : te.z;
-        const int nb[6] = {(int)(tx & 0xFFFFu), (int)(tx >> 16), (int)(te.x & 0xFFFFu), (int)(te.x >> 16),
-                           (int)(te.y & 0xFFFFu), (int)(te.y >> 16)};
+        const uint32_t off[6] = {tx & 0xFFFFu, tx >> 16, te.x & 0xFFFFu, te.x >> 16, te.y & 0xFFFFu, te.y >> 16};
         const uint32_t Sv = Sp[h];
         uint32_t X[6];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) X[j] = So[nb[j]];
+        for (int j = 0; j < 6; ++j) X[j] = *(const uint32_t *)((const char *)So + off[j]);
         const u32x4 rk = {k == 0 ? rw[0].x : k == 1 ? rw[0].y : k == 2 ? rw[0].z : rw[0].w,
                           k == 0 ? rw[1].x : k == 1 ? rw[1].y : k == 2 ? rw[1].z : rw[1].w,
                           k == 0 ? rw[2].x : k == 1 ? rw[2].y : k == 2 ? rw[2].z : rw[2].w,
@@ -114,8 +118,10 @@ __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &
         if constexpr (JK == 0) {
             // bonds +x, -x, +y, -y, +z, -z: own +d bonds, the neighbours' +d bonds for -d
             const int *Jp = (const int *)Jl + (size_t)P * 3 * HALF, *Jo = (const int *)Jl + (size_t)(1 - P) * 3 * HALF;
-            const int jx = Jp[h], jxm = Jo[nb[1]], jy = Jp[HALF + h], jym = Jo[HALF + nb[3]];
-            const int jz = Jp[2 * HALF + h], jzm = Jo[2 * HALF + nb[5]];
+            const char *Jb = (const char *)Jo;
+            const int jx = Jp[h], jxm = *(const int *)(Jb + off[1]), jy = Jp[HALF + h];
+            const int jym = *(const int *)(Jb + 4 * HALF + off[3]);
+            const int jz = Jp[2 * HALF + h], jzm = *(const int *)(Jb + 8 * HALF + off[5]);
             const int Ja[4] = {jx, jx, jx, jx}, Js[4] = {jxm, jxm, jxm, jxm};
             const int Jy[4] = {jy, jy, jy, jy}, Jyn[4] = {jym, jym, jym, jym};
             const int Jz[4] = {jz, jz, jz, jz}, Jzn[4] = {jzm, jzm, jzm, jzm};
@@ -128,8 +134,8 @@ __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &
             // bond-spin product bytes J s_j: 0x01 (+1) or 0xFF (-1); c counts the -1
             const int8_t *Jp = (const int8_t *)Jl + (size_t)P * 3 * HALF;
             const int8_t *Jo = (const int8_t *)Jl + (size_t)(1 - P) * 3 * HALF;
-            const int8_t jb[6] = {Jp[h], Jo[nb[1]], Jp[HALF + h], Jo[HALF + nb[3]], Jp[2 * HALF + h],
-                                  Jo[2 * HALF + nb[5]]};
+            const int8_t jb[6] = {Jp[h], Jo[off[1] >> 2], Jp[HALF + h], Jo[HALF + (off[3] >> 2)], Jp[2 * HALF + h],
+                                  Jo[2 * HALF + (off[5] >> 2)]};
             constexpr uint32_t LOW = 0x01010101u;
             uint32_t cnt = 0;
 #pragma unroll

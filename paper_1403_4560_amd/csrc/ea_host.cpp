@@ -156,6 +156,7 @@ struct ea_ensemble {
         int wbegin, wcount;  // HBM tier: range of the walker table
         bool bits;           // multispin engine
         bool group;          // walker-interleaved engine
+        int group_min_threads = 64;
     };
     std::vector<Class> classes;
     std::vector<int> item_pos;  // sample -> index of its chain-a item in the sorted item list
@@ -598,8 +599,12 @@ hipError_t launch_class(ea_ensemble *e, const ea_ensemble::Class &c, int K, int 
     SweepArgs A = sweep_args(e, K, (const int32_t *)e->items.p + first, n_items);
     SweepFn fn = sweep_fn(c.L, e->jkind, c.row, c.bits, c.group, unbatched);
     if (!fn) return hipErrorInvalidDeviceFunction;
-    const int threads = c.row || c.bits ? c.threads : c.group ? std::min(c.threads, e->plan.threads)
-                                                              : e->plan.threads;
+    // the group engine takes at most the plan's size, but never so few threads
+    // that one thread holds more than 16 site groups per half-sweep (its int32
+    // energy tallies)
+    const int threads = c.row || c.bits ? c.threads
+                        : c.group ? std::max(std::min(c.threads, e->plan.threads), c.group_min_threads)
+                                  : e->plan.threads;
     hipLaunchKernelGGL(fn, dim3(n_items), dim3(threads), c.lds, e->stream, A);
     return hipGetLastError();
 }
@@ -971,9 +976,20 @@ std::vector<int> batch_candidates(const ea_ensemble *e, size_t ci)
     std::vector<int> out;
     const auto &c = e->classes[ci];
     const int need = batch_need(c);
+    if (need <= 0) return out;
+    // the row engine needs a thread per (walker, column); the group and site
+    // engines take any team, the group engine one that keeps a thread's share of
+    // an item's sites per half-sweep within 64 (its int32 energy tallies)
+    int min_threads = c.row ? need : 64;
+    if (c.group) {
+        int nTmax = 1;
+        for (int i = 0; i < c.count; i += 2) nTmax = std::max(nTmax, e->smp[e->sorted_samples[(c.begin + i) / 2]].nT);
+        const int items = group_items(c.L, nTmax);
+        min_threads = std::max(min_threads, (items / 16 + 63) / 64 * 64);
+    }
     const size_t ldsc = (c.lds + 15) & ~(size_t)15;
     for (int P = 1; P <= 8; P *= 2)
-        if (need > 0 && BATCH_THREADS / P >= need && P * ldsc <= e->lds_max) out.push_back(P);
+        if (BATCH_THREADS / P >= min_threads && P * ldsc <= e->lds_max) out.push_back(P);
     return out;
 }
 
@@ -1157,6 +1173,7 @@ ea_status ea_create_ensemble(const ea_desc *d, void *hip_stream, ea_ensemble **o
             } else if (h.group) {
                 c.lds = std::max(c.lds, group_lds_offsets(h.L, h.nT, e->jkind).total);
                 c.threads = std::max(c.threads, group_threads(h.L, h.nT));
+                c.group_min_threads = std::max(c.group_min_threads, (group_items(h.L, h.nT) / 16 + 63) / 64 * 64);
             } else {
                 c.lds = std::max(c.lds, lds_offsets(h.L, h.nT, e->jkind).total);
                 const bool row = d->tier != EA_TIER_SITE && row_engine(h.L, h.nT, e->jkind);
