@@ -110,11 +110,12 @@ typedef struct {
     int32_t threads;    /* threads per workgroup of the site engine's own
                            launches: 256, 512 or 1024                           */
     int32_t use_graph;  /* 1: replay each chunk from a captured hipGraph       */
-    int32_t batch;      /* 1: the lattice-size classes of the group, site and
-                           L = 8 row engines run as one persistent launch per
-                           chunk (a queue of units, longest first, each unit
-                           up to P items of one class run side by side by P
-                           teams of a workgroup; P per class is chosen by
+    int32_t batch;      /* 1: the lattice-size classes of the group engine,
+                           the L = 8 row engine and the L <= 4 site engine
+                           run as one launch per chunk (one workgroup per
+                           unit, units ordered longest first, each unit up to
+                           P items of one class run side by side by P teams
+                           of a workgroup; P per class is chosen by
                            ea_autotune); 0: one launch per class.  Default 1
                            when two or more such classes exist.             */
 } ea_plan;
@@ -257,8 +258,10 @@ ea_status ea_autotune(ea_ensemble *ens, int32_t trial_sweeps);
  * be NULL.  teams[c] = work items of class c that one batch workgroup runs
  * side by side (1, 2, 4 or 8 teams of 512/teams threads), 0 for a class the
  * batch launch does not take (one-bit, HBM-resident, and row-engine L = 16
- * classes keep their own launches).  signature (17 bytes, may be NULL)
- * receives the key under which ea_autotune caches this ensemble's plan. */
+ * classes keep their own launches).  With the batch launch off, a group-engine
+ * class runs its own launch with workgroups of the same team size.
+ * signature (17 bytes, may be NULL) receives the key under which ea_autotune
+ * caches this ensemble's plan. */
 ea_status ea_get_batch_plan(const ea_ensemble *ens, int32_t *n_classes, int32_t *class_L, int32_t *class_engine,
                             int32_t *teams, char *signature);
 

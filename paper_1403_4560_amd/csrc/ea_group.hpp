@@ -5,8 +5,8 @@
 // Layout: one int8x4 word holds one site of four walkers of a chain (a
 // "quad"), [2 parities][quads][N/2 + 1 sites] (the odd plane stride spreads
 // the quads of a wave over all LDS banks); a per-item table gives every
-// sublattice site its six neighbours in the other sublattice as 16-bit
-// indices (both checkerboard offsets for x); a site's six neighbour words and
+// sublattice site its six neighbours in the other sublattice as 16-bit byte
+// offsets (both checkerboard offsets for x); a site's six neighbour words and
 // six bonds serve four Metropolis attempts at once and the neighbour
 // arithmetic works for any L (the four sites of a Philox group may lie in
 // different rows).  A work item is (quad, group of four consecutive sublattice
@@ -73,7 +73,7 @@ __device__ __forceinline__ uint4 nbr_entry(int h)
 }
 
 struct GroupLane {
-    float cl[4];            // two_beta_log2e of each walker's slot
+    float ka[4], kb[4];     // per walker: the folded exponent's constants (update_word_gauss)
     uint32_t c2[4];         // Philox counter word 2 of each walker
     uint32_t thr[4];        // +-1: offset of each walker's threshold table in lut
     uint32_t valid;         // 0xFF in the bytes of real walkers
@@ -84,7 +84,7 @@ struct GroupTally {
     uint32_t flips = 0;     // per byte: flipped sites of that walker
     uint32_t fdown = 0;     // per byte: flipped sites that were -1
     uint32_t nd = 0;        // per byte, second half: -1 spins after the update
-    int accE[4] = {0, 0, 0, 0};  // second half: sum of (S_u XOR m') per walker
+    int accE[4] = {0, 0, 0, 0};  // second half: sum of (S_u + hgrid) XOR m' per walker (Gaussian)
 };
 
 // Metropolis update of work item (quad q, sites 4 g4 .. 4 g4 + 3) of parity P.
@@ -126,9 +126,10 @@ __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &
             const int Jy[4] = {jy, jy, jy, jy}, Jyn[4] = {jym, jym, jym, jym};
             const int Jz[4] = {jz, jz, jz, jz}, Jzn[4] = {jzm, jzm, jzm, jzm};
             // the exact path reads 2 beta32 of walker i's slot, t = bits 1 .. 27 of its counter word
-            fm = update_word_gauss<false>(Sv, X[0], X[1], X[2], X[3], X[4], X[5], Ja, Js, Jy, Jyn, Jz, Jzn, rk,
-                                          ln.cl, ln.cl, [&](int i) { return 2.0f * b32[(ln.c2[i] >> 1) & 0x7FFFFFFu]; },
-                                          ln.h32, 0, Sus) &
+            // Sus = S_u + hgrid (the field's grid part folded into the integer field)
+            fm = update_word_gauss<true>(Sv, X[0], X[1], X[2], X[3], X[4], X[5], Ja, Js, Jy, Jyn, Jz, Jzn, rk,
+                                         ln.ka, ln.kb, [&](int i) { return 2.0f * b32[(ln.c2[i] >> 1) & 0x7FFFFFFu]; },
+                                         ln.h32, d.hgrid, Sus) &
                  ln.valid;
         } else {
             // bond-spin product bytes J s_j: 0x01 (+1) or 0xFF (-1); c counts the -1
@@ -249,7 +250,9 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         for (int i = 0; i < 4; ++i) {
             const int w = 4 * q + i;
             ts[i] = w < nT ? I.sow[w] : 0;
-            ln.cl[i] = two_beta_log2e(I.b32[ts[i]]);
+            const float cp = two_beta_log2e(I.b32[ts[i]]);
+            ln.ka[i] = cp * 0x1p-18f;
+            ln.kb[i] = cp * (d.h32 - (float)d.hgrid * 0x1p-18f);
             ln.c2[i] = (PURPOSE_METROPOLIS << 28) | ((uint32_t)ts[i] << 1) | (uint32_t)r;
             ln.thr[i] = 14 * ts[i];
         }
@@ -266,6 +269,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         __syncthreads();
         if (on) {
             const uint32_t c1 = (uint32_t)(2 * n + 1);
+            const int items1 = (G4 - gs + TPQ - 1) / TPQ;  // site groups of this thread
 #pragma unroll 1
             for (int g4 = gs; g4 < G4; g4 += TPQ)
                 group_item<L, JK, 1>(A, d, SG, Jl, lut, I.b32, NB, NQ, q, g4, c1, ln, ty);
@@ -274,8 +278,12 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
                 if (w >= nT) break;
                 const int fl = (int)((ty.flips >> (8 * i)) & 0xFFu), fd = (int)((ty.fdown >> (8 * i)) & 0xFFu);
                 const int nd = (int)((ty.nd >> (8 * i)) & 0xFFu);
-                // dEJ collects minus the new E_J (all threads of the quad add)
-                atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)((long long)ty.accE[i] + nd));
+                // dEJ collects minus the new E_J (all threads of the quad add);
+                // Gaussian couplings: the tallies summed s' (S_u + hgrid) over
+                // this thread's 4 * items1 odd sites, so take hgrid sum s' out
+                long long sE = (long long)ty.accE[i] + nd;
+                if constexpr (JK == 0) sE -= (long long)d.hgrid * (4 * items1 - 2 * nd);
+                atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)sE);
                 atomicAdd(&I.dM[w], -2 * (fl - 2 * fd));
                 atomicAdd(&I.fl[ts[i]], fl);
             }
@@ -295,16 +303,29 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         if (done == next_meas) {
             next_meas += A.measure_every;
             uint32_t *dst = A.frames + f * A.frame_words + d.frame_off + (size_t)r * nT * L * L;
-            for (int i = tid; !tm.ghost && i < nT * L * L; i += T) {
-                const int t = i / (L * L), row = i - t * (L * L);
-                const int w = I.was[t], wq = w >> 2, sh = 8 * (w & 3) + 7;
-                const int yz = (row % L) + row / L;
-                uint32_t bits = 0;
+            // One (quad, row) per step: the row's L words hold the four walkers'
+            // spins; their sign bits, moved to bit 0 of each byte and shifted by
+            // x, build the four walkers' rows at once (byte b of lo: x < 8, of
+            // hi: x >= 8).  Site x of row (y, z) is sublattice site
+            // row L/2 + x/2 of parity (x + y + z) & 1.
+            constexpr int HL = L / 2, PS = HALF + 1;
+            for (int i = tid; !tm.ghost && i < NQ * L * L; i += T) {
+                const int q = i / (L * L), row = i - q * (L * L);
+                const int e = ((row % L) + row / L) & 1;  // parity of the even x
+                const uint32_t *ev = SG + (e * NQ + q) * PS + row * HL;
+                const uint32_t *od = SG + ((1 - e) * NQ + q) * PS + row * HL;
+                uint32_t lo = 0, hi = 0;
+#pragma unroll
                 for (int x = 0; x < L; ++x) {
-                    const int p = (x + yz) & 1, h = (x + L * row) >> 1;
-                    bits |= ((SG[gidx<L>(p, h, wq, NQ)] >> sh) & 1u) << x;
+                    const uint32_t sg = (((x & 1) ? od : ev)[x >> 1] >> 7) & 0x01010101u;
+                    if (x < 8) lo |= sg << x;
+                    else hi |= sg << (x - 8);
                 }
-                dst[i] = bits;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int w = 4 * q + b;
+                    if (w < nT) dst[I.sow[w] * L * L + row] = ((lo >> (8 * b)) & 0xFFu) | (((hi >> (8 * b)) & 0xFFu) << 8);
+                }
             }
             for (int t = tid; !tm.ghost && t < nT; t += T) {
                 const int w = I.was[t];

@@ -31,9 +31,9 @@ template <int L, int JK, int VAR> __global__ void hbm_half_kernel(SweepArgs A);
 __global__ void hbm_exchange_kernel(SweepArgs A);
 __global__ void hbm_snapshot_kernel(SweepArgs A);
 template <int L> __global__ void measure_kernel(MeasureArgs A);
+__global__ void measure_all_kernel(MeasureArgs A);
 __global__ void advance_kernel(int64_t *state, int64_t k);
 template <int JK> __global__ void batch_sweep_kernel(SweepArgs A, BatchArgs B);
-__global__ void batch_reset_kernel(int32_t *counter);
 __global__ void exp_bracket_kernel(uint32_t, uint32_t, unsigned long long *, unsigned int *);
 template <int JK>
 __global__ void energy_kernel(const SampleDev *, const int32_t *, const int8_t *, const void *, int64_t *,
@@ -140,9 +140,9 @@ struct ea_ensemble {
     std::vector<char> sel_seen;     // [S]
     DevBuf jkrep;                   // jackknife replicates, grown on demand
     // batch launch (ea_batch.hip) of the classes of the small LDS-resident engines
-    DevBuf batchbuf;                // queue counter (first 256 bytes), then the units
+    DevBuf batchbuf;                // 256 reserved bytes, then the units (longest first)
     std::vector<int> class_P;       // per class: teams per batch workgroup, 0 = not batchable
-    int n_units = 0, batch_grid = 0;
+    int n_units = 0;
     size_t batch_lds = 0;
     int cus = 0;                    // compute units of the device
     size_t lds_per_cu = 0, lds_max = 0;
@@ -428,6 +428,19 @@ MeasureFn measure_fn(int L)
 // launch per lattice size, one wave per slot.
 hipError_t launch_measure(ea_ensemble *e, int K, int explicit_frames)
 {
+    // lattice sizes up to 16: one launch for every slot
+    bool small = true;
+    int total = 0;
+    for (const auto &c : e->slot_classes) {
+        small &= c.L <= LDS_MAX_L;
+        total += c.count;
+    }
+    if (small && e->slot_classes.size() > 1) {
+        MeasureArgs M = measure_args(e, K, explicit_frames);
+        M.slots = (const int32_t *)e->mslots.p;
+        hipLaunchKernelGGL(measure_all_kernel, dim3((unsigned)total), dim3(64), 0, e->stream, M);
+        return hipGetLastError();
+    }
     for (const auto &c : e->slot_classes) {
         MeasureArgs M = measure_args(e, K, explicit_frames);
         M.slots = (const int32_t *)e->mslots.p + c.begin;
@@ -599,25 +612,29 @@ hipError_t launch_class(ea_ensemble *e, const ea_ensemble::Class &c, int K, int 
     SweepArgs A = sweep_args(e, K, (const int32_t *)e->items.p + first, n_items);
     SweepFn fn = sweep_fn(c.L, e->jkind, c.row, c.bits, c.group, unbatched);
     if (!fn) return hipErrorInvalidDeviceFunction;
-    // the group engine takes at most the plan's size, but never so few threads
-    // that one thread holds more than 16 site groups per half-sweep (its int32
-    // energy tallies)
+    // the group engine runs the team size the plan gives its class (the batch
+    // launch's teams: BATCH_THREADS / teams per workgroup), which keeps a
+    // thread's share within 16 site groups per half-sweep (its int32 energy
+    // tallies); the site engine runs the plan's workgroup size
+    const size_t ci = (size_t)(&c - e->classes.data());
     const int threads = c.row || c.bits ? c.threads
-                        : c.group ? std::max(std::min(c.threads, e->plan.threads), c.group_min_threads)
+                        : c.group ? (e->class_P[ci] > 0 ? BATCH_THREADS / e->class_P[ci]
+                                                        : std::max(std::min(c.threads, e->plan.threads),
+                                                                   c.group_min_threads))
                                   : e->plan.threads;
     hipLaunchKernelGGL(fn, dim3(n_items), dim3(threads), c.lds, e->stream, A);
     return hipGetLastError();
 }
 
 // Batch launch.  A class is batchable if its engine is one the batch kernel
-// runs (group, site, or row at L = 8) and its items fit a team of at most
-// BATCH_THREADS threads.
+// runs (group, row at L = 8, site at L <= 4) and its items fit a team of at
+// most BATCH_THREADS threads.
 int batch_need(const ea_ensemble::Class &c)
 {
     if (c.hbm || c.bits) return 0;
     if (c.row) return c.L == 8 && c.threads <= BATCH_THREADS ? c.threads : 0;
     if (c.group) return c.threads <= BATCH_THREADS ? c.threads : 0;
-    return 64;  // site engine: any team size
+    return c.L <= 4 ? 64 : 0;  // site engine (tiny chains): any team size
 }
 
 int batch_kind(const ea_ensemble::Class &c)
@@ -635,8 +652,8 @@ int default_P(int need)
 
 bool batch_active(const ea_ensemble *e) { return e->plan.batch && e->n_units > 0; }
 
-// Units of every batchable class (class_P[c] teams per workgroup), queued
-// longest first, with the grid and LDS of the launch; uploaded to the device.
+// Units of every batchable class (class_P[c] teams per workgroup), ordered
+// longest first, with the LDS of the launch; uploaded to the device.
 ea_status build_batch(ea_ensemble *e)
 {
     std::vector<std::pair<double, BatchUnit>> q;
@@ -668,8 +685,6 @@ ea_status build_batch(ea_ensemble *e)
     if (q.empty()) return EA_OK;
     if ((size_t)e->n_units * sizeof(BatchUnit) + 256 > e->batchbuf.bytes)
         return fail(EA_EINVAL, "internal error: %d batch units exceed the unit table", e->n_units);
-    const int wpc = (int)std::max<size_t>(1, std::min<size_t>(2, e->lds_per_cu / std::max<size_t>(lds, 1)));
-    e->batch_grid = std::min(e->n_units, e->cus * wpc);
     std::vector<BatchUnit> units(q.size());
     for (size_t i = 0; i < q.size(); ++i) units[i] = q[i].second;
     HIP_TRY(e, hipMemcpyAsync((char *)e->batchbuf.p + 256, units.data(), sizeof(BatchUnit) * units.size(),
@@ -681,19 +696,16 @@ ea_status build_batch(ea_ensemble *e)
 
 hipError_t launch_batch(ea_ensemble *e, int K)
 {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, e->stream, (int32_t *)e->batchbuf.p);
-    hipError_t st = hipGetLastError();
-    if (st != hipSuccess) return st;
     SweepArgs A = sweep_args(e, K, (const int32_t *)e->items.p, 2 * e->S);
     BatchArgs B{};
     B.units = (const BatchUnit *)((const char *)e->batchbuf.p + 256);
     B.n_units = e->n_units;
-    B.counter = (int32_t *)e->batchbuf.p;
+    B.counter = nullptr;
     if (e->jkind == EA_J_GAUSS_F32)
-        hipLaunchKernelGGL(batch_sweep_kernel<0>, dim3((unsigned)e->batch_grid), dim3(BATCH_THREADS), e->batch_lds,
+        hipLaunchKernelGGL(batch_sweep_kernel<0>, dim3((unsigned)e->n_units), dim3(BATCH_THREADS), e->batch_lds,
                            e->stream, A, B);
     else
-        hipLaunchKernelGGL(batch_sweep_kernel<1>, dim3((unsigned)e->batch_grid), dim3(BATCH_THREADS), e->batch_lds,
+        hipLaunchKernelGGL(batch_sweep_kernel<1>, dim3((unsigned)e->n_units), dim3(BATCH_THREADS), e->batch_lds,
                            e->stream, A, B);
     return hipGetLastError();
 }
@@ -1744,9 +1756,10 @@ ea_status ea_autotune(ea_ensemble *e, int32_t trial_sweeps)
     };
     double best_ms = 0.0;
     result = trial(&best_ms);
-    // 1. teams per batch workgroup, class by class (coordinate descent), when
-    //    the batch launch is on
-    if (result == EA_OK && e->plan.batch && e->n_units > 0) {
+    // 1. team size per class, class by class (coordinate descent): the batch
+    //    launch's teams per workgroup, or the group engine's workgroup size in
+    //    its own launches
+    auto tune_teams = [&]() {
         for (size_t ci = 0; ci < e->classes.size() && result == EA_OK; ++ci) {
             if (e->class_P[ci] <= 0) continue;
             const int keepP = e->class_P[ci];
@@ -1765,14 +1778,20 @@ ea_status ea_autotune(ea_ensemble *e, int32_t trial_sweeps)
             e->class_P[ci] = bestP;
             if (result == EA_OK) result = build_batch(e);
         }
-    }
-    // 2. one batch launch against one launch per class
+    };
+    if (e->n_units > 0) tune_teams();
+    // 2. one batch launch against one launch per class (then the teams again
+    //    if the other form won)
     if (result == EA_OK && e->n_units > 0) {
         e->plan.batch ^= 1;
         double ms = 0.0;
         result = trial(&ms);
-        if (result == EA_OK && ms < best_ms) best_ms = ms;
-        else e->plan.batch ^= 1;
+        if (result == EA_OK && ms < best_ms) {
+            best_ms = ms;
+            tune_teams();
+        } else {
+            e->plan.batch ^= 1;
+        }
     }
     // 3. workgroup size of the site engine's own launches
     bool site_launch = false;

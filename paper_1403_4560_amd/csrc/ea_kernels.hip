@@ -352,20 +352,39 @@ __device__ __forceinline__ void column_counts(const uint32_t *eqr, int lane, int
     }
 }
 
+// LDS of one slot's measurement.
 template <int L>
-__global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
+struct MeasLds {
+    static constexpr int LP = L + 1, GC = 64 / L;  // GC: chunks of v per plane count
+    double accs[NACC];
+    double re_f[NPLANE], im_f[NPLANE];
+    double cst[L], snt[L];  // cos and sin of 2 pi c / L
+    uint32_t eqr[L * LP];
+    int C[L * LP], D[L * LP], R[L * LP];
+    int P[NPLANE][L];
+    int part[NPLANE][GC][L];
+};
+
+// The measurement of slot A.slots[slot_index] by one wave, with its LDS at buf.
+template <int L>
+__device__ __forceinline__ void measure_slot(const MeasureArgs &A, int slot_index, char *buf)
 {
     constexpr int L2 = L * L, LP = L + 1;
     constexpr uint32_t mask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
-    __shared__ uint32_t eqr[L * LP];
-    __shared__ int C[L * LP], D[L * LP], R[L * LP];
-    constexpr int GC = 64 / L;  // chunks of v per plane count
-    __shared__ int P[NPLANE][L];
-    __shared__ int part[NPLANE][GC][L];
-    __shared__ double accs[NACC];
-    __shared__ double re_f[NPLANE], im_f[NPLANE];
-    __shared__ double cst[L], snt[L];  // cos and sin of 2 pi c / L
-    const int gs = A.slots[blockIdx.x];
+    constexpr int GC = MeasLds<L>::GC;
+    MeasLds<L> &S = *reinterpret_cast<MeasLds<L> *>(buf);
+    auto &eqr = S.eqr;
+    auto &C = S.C;
+    auto &D = S.D;
+    auto &R = S.R;
+    auto &P = S.P;
+    auto &part = S.part;
+    auto &accs = S.accs;
+    auto &re_f = S.re_f;
+    auto &im_f = S.im_f;
+    auto &cst = S.cst;
+    auto &snt = S.snt;
+    const int gs = A.slots[slot_index];
     const int s = A.slot_sample[gs];
     const SampleDev d = A.samples[s];
     const int t = gs - d.slot_off;
@@ -469,6 +488,28 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
         __syncthreads();
     }
     for (int i = tid; i < NACC; i += T) A.acc[(size_t)gs * NACC + i] = accs[i];
+}
+
+template <int L>
+__global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
+{
+    __shared__ __attribute__((aligned(16))) char buf[sizeof(MeasLds<L>)];
+    measure_slot<L>(A, blockIdx.x, buf);
+}
+
+// Every slot of lattice sizes up to 16 in one launch (one wave per slot, the
+// slot's own lattice size chosen per workgroup; LDS sized for L = 16).
+__global__ void __launch_bounds__(64) measure_all_kernel(MeasureArgs A)
+{
+    __shared__ __attribute__((aligned(16))) char buf[sizeof(MeasLds<16>)];
+    const int L = A.samples[A.slot_sample[A.slots[blockIdx.x]]].L;
+#define EA_M(Lv) \
+    case Lv: measure_slot<Lv>(A, blockIdx.x, buf); break;
+    switch (L) {
+        EA_M(2) EA_M(4) EA_M(6) EA_M(8) EA_M(10) EA_M(12) EA_M(14) EA_M(16)
+    default: break;
+    }
+#undef EA_M
 }
 
 #define EA_MEAS(Lv) template __global__ void measure_kernel<Lv>(MeasureArgs);

@@ -358,7 +358,11 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
     // row engine: this thread's walker and column (see RowMap)
     constexpr int CPW = RowMap<(L >= 8 ? L : 8)>::CPW, WPW = RowMap<(L >= 8 ? L : 8)>::WPW;
     constexpr int WPR = L / 8 > 0 ? L / 8 : 1;
-    const int rw_wave = tid >> 6, rw_lane = tid & 63;
+    // (from an opaque copy of the thread index: derived here, after the loads,
+    // not hoisted to the kernel's start and kept across them, which spills)
+    int tid_r = tid;
+    asm volatile("" : "+v"(tid_r));
+    const int rw_wave = tid_r >> 6, rw_lane = tid_r & 63;
     const int rw_par = __builtin_amdgcn_readfirstlane(rw_wave & 1);
     const int rw_rem = rw_lane % CPW;
     const int rw_w = (rw_wave >> 1) * WPW + rw_lane / CPW;
@@ -433,8 +437,14 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
         }
     }
     __syncthreads();
-    if (!tm.ghost) copy_walkers(I.S, item_walker_stride(L), A.spins + sbase, nT, N, false, tm);
-    for (int i = tid; !tm.ghost && i < nT; i += T) {
+    // Write-back addresses are derived again from an opaque copy of the thread
+    // index rather than kept from the load phase: held across the sweep loop
+    // they would be spilled to scratch memory (the L = 16 row kernel uses
+    // every register it may have).
+    Team tw = tm;
+    asm volatile("" : "+v"(tw.tid));
+    if (!tw.ghost) copy_walkers(I.S, item_walker_stride(L), A.spins + sbase, nT, N, false, tw);
+    for (int i = tw.tid; !tw.ghost && i < nT; i += T) {
         A.was[gi + i] = I.was[i];
         A.EJ[gi + i] = I.EJ[i];
         A.M[gi + i] = I.M[i];

@@ -109,11 +109,11 @@ struct MeasureArgs {
     int64_t measure_start;
 };
 
-// Batch launch (ea_batch.hip): one persistent launch runs the work items of
-// every lattice-size class of the small LDS-resident engines.  A unit is up to
-// P items of one class that P equal, wave-aligned teams of a workgroup run
-// side by side; workgroups take units from a queue ordered by decreasing cost
-// (longest first), so no class waits for another's tail.
+// Batch launch (ea_batch.hip): one launch runs the work items of every
+// lattice-size class of the small LDS-resident engines.  A unit is up to P
+// items of one class that P equal, wave-aligned teams of a workgroup run side
+// by side; one workgroup per unit, units ordered by decreasing cost (longest
+// first), so no class waits for another's tail.
 enum { BATCH_SITE = 0, BATCH_ROW = 1, BATCH_GROUP = 2 };
 constexpr int BATCH_THREADS = 512;
 
@@ -130,7 +130,7 @@ struct BatchArgs {
     const BatchUnit *units;
     int32_t n_units;
     int32_t pad;
-    int32_t *counter;  // next unit of the queue; zeroed before every launch
+    int32_t *counter;  // reserved
 };
 
 // Number of measurement sweeps among completed-sweep counts 1..x.
