@@ -88,7 +88,8 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the factors a plain copy of
 # known size reads), keyed by a fingerprint of the kernel sources they were
 # taken on; reported as null once the kernels change.
-MEASURED_TRAFFIC = {"L16_gauss": ("b11a8e83f689c066", 2.2589e9), "L32_pm1": ("b11a8e83f689c066", 3.5384e9)}
+MEASURED_TRAFFIC = {"L16_gauss": ("2079493e10d59eae", 2.0324e9), "L32_pm1": ("2079493e10d59eae", 3.5385e9),
+                    "mixed_L6_12": ("2079493e10d59eae", 0.7663e9)}
 KERNEL_SOURCES = tuple("paper_1403_4560_amd/csrc/" + f for f in (
     "ea_kernels.hip", "ea_bits.hip", "ea_group.hip", "ea_batch.hip", "ea_row.hpp", "ea_group.hpp", "ea_item.hpp",
     "ea_update.hpp", "ea_device.hpp", "ea_types.hpp"))
