@@ -55,7 +55,9 @@ __device__ __forceinline__ int gidx(int p, int h, int q, int NQ)
     return (p * NQ + q) * PS + h;
 }
 
-// Neighbour table entry of sublattice site h: the byte offsets 4 n of its
+// Neighbour table entry of sublattice site h, stored at (h & 3) N/8 + h / 4
+// (the lanes of a wave read one site of consecutive site groups: contiguous
+// 16-byte entries, free of bank conflicts): the byte offsets 4 n of its
 // neighbour words (and of their int32 bonds) in 16-bit halves, {+y | -y << 16,
 // +z | -z << 16, +x | -x << 16 for parity 0, the same for parity 1}, so that
 // an address is one add of a half-word to a base (4 n < 2^16 for L <= 16).
@@ -102,7 +104,7 @@ __device__ __forceinline__ void group_item(const SweepArgs &A, const SampleDev &
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int h = 4 * g4 + k;
-        const uint4 te = NB[h];
+        const uint4 te = NB[k * (HALF / 4) + g4];
         const uint32_t tx = P ? te.w : te.z;
         const uint32_t off[6] = {tx & 0xFFFFu, tx >> 16, te.x & 0xFFFFu, te.x >> 16, te.y & 0xFFFFu, te.y >> 16};
         const uint32_t Sv = Sp[h];
@@ -204,7 +206,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         }
         SG[gidx<L>(ph / HALF, ph % HALF, q, NQ)] = wv;
     }
-    for (int h = tid; h < HALF; h += T) NB[h] = nbr_entry<L>(h);
+    for (int h = tid; h < HALF; h += T) NB[(h & 3) * G4 + (h >> 2)] = nbr_entry<L>(h);
     if constexpr (JK == 0) {
         // couplings as exact int32 multiples of 2^-18
         const float4 *src = (const float4 *)((const float *)A.J + d.J_off);  // J_off is a multiple of 4
@@ -221,9 +223,9 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     for (int i = tid; i < nT; i += T) {
         I.was[i] = A.was[gi + i];
         I.sow[A.was[gi + i]] = i;  // kept by exchange_pass from here on
-        I.dEJ[i] = 0;
+        // walker totals: E_J = -dEJ, magnetisation M + dM (see the sweep loop)
+        I.dEJ[i] = -A.EJ[gi + i];
         I.dM[i] = 0;
-        I.EJ[i] = A.EJ[gi + i];
         I.M[i] = A.M[gi + i];
         I.fl[i] = 0;
         I.sw[i] = 0;
@@ -240,11 +242,23 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     for (int i = 0; i < 4; ++i) valid |= (4 * q + i < nT ? 0xFFu : 0u) << (8 * i);
     const double unit = JK == 0 ? 0x1p-18 : 1.0;
     const double hd = (double)d.h32;
+    const int hg = JK == 0 ? d.hgrid : 0;  // the field's grid part folded into S_u
     const int64_t n0 = A.state[0];
     int64_t next_meas = next_measurement(n0, A.measure_every, A.measure_start);
     int64_t f = 0;  // frame of the next measurement within this chunk
+    // Energy of walker w after a sweep: its second half-sweep's tallies leave
+    // minus E_J in dEJ and the magnetisation change in dM; both are folded in
+    // at the start of the next sweep, before its own tallies (which follow the
+    // first half-sweep's barrier), so no pass of their own is needed.
+    const auto energy = [&](int w) { return (double)(-I.dEJ[w]) * unit - hd * (double)(I.M[w] + I.dM[w]); };
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
+        #pragma unroll 1
+        for (int i = tid; i < nT; i += T) {
+            I.M[i] += I.dM[i];
+            I.dM[i] = 0;
+            I.dEJ[i] = -(long long)hg * HALF;
+        }
         GroupLane ln;
         int ts[4];
         for (int i = 0; i < 4; ++i) {
@@ -269,34 +283,60 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         __syncthreads();
         if (on) {
             const uint32_t c1 = (uint32_t)(2 * n + 1);
-            const int items1 = (G4 - gs + TPQ - 1) / TPQ;  // site groups of this thread
 #pragma unroll 1
             for (int g4 = gs; g4 < G4; g4 += TPQ)
                 group_item<L, JK, 1>(A, d, SG, Jl, lut, I.b32, NB, NQ, q, g4, c1, ln, ty);
+        }
+        // Per-walker tallies (idle lanes hold zeros).  dEJ collects minus the
+        // new E_J: the second half-sweep summed (S_u + hgrid) XOR m' = s'(S_u +
+        // hgrid) - [s' = -1] over the odd sites, so a thread adds accE +
+        // (1 + 2 hgrid) nd and dEJ starts the sweep at -hgrid N/2 (+-1
+        // couplings: hgrid = 0).  Per thread a byte counter holds at most 128
+        // (at most 16 site groups per half-sweep), so a sum over 16 lanes fits
+        // a 16-bit lane.  Teams of four or more waves with NQ = 1, 2 or 4 sum
+        // the lanes of a row of 16 that share a quad (lane = quad mod NQ)
+        // first (byte counters as 16-bit lanes, walkers 0 and 2 in one word,
+        // 1 and 3 in another); lane j of the row then adds walker (j / NQ) mod
+        // 4 of quad j mod NQ, so a wave issues three LDS atomics, not twelve.
+        const long long hg1 = 2 * (long long)hg + 1;
+        if (T >= 256 && NQ <= 4 && NQ != 3) {
+            uint32_t c[6] = {ty.flips & 0x00FF00FFu, (ty.flips >> 8) & 0x00FF00FFu,
+                             ty.fdown & 0x00FF00FFu, (ty.fdown >> 8) & 0x00FF00FFu,
+                             ty.nd & 0x00FF00FFu,    (ty.nd >> 8) & 0x00FF00FFu};
+            for (int k = 0; k < 6; ++k) c[k] = (uint32_t)row_residue_sum((int)c[k], NQ);
+            long long e[4];
+            for (int i = 0; i < 4; ++i) e[i] = row_residue_sum((long long)ty.accE[i], NQ);
+            // (lane roles from an opaque copy of the thread index: derived per
+            // sweep, not hoisted out of the item loop and spilled)
+            int tl = tid;
+            asm volatile("" : "+v"(tl));
+            // (NQ = 1, 2, 4: j / NQ = j >> (NQ >> 1))
+            const int j = tl & 15, sel = (j >> (NQ >> 1)) & 3, w = 4 * (tl & (NQ - 1)) + sel, sh = 16 * (sel >> 1);
+            const bool odd = sel & 1;
+            const int fl = (int)(((odd ? c[1] : c[0]) >> sh) & 0xFFFFu);
+            const int fd = (int)(((odd ? c[3] : c[2]) >> sh) & 0xFFFFu);
+            const int nd = (int)(((odd ? c[5] : c[4]) >> sh) & 0xFFFFu);
+            const long long ea = sel == 0 ? e[0] : sel == 1 ? e[1] : sel == 2 ? e[2] : e[3];
+            const int t = sel == 0 ? ts[0] : sel == 1 ? ts[1] : sel == 2 ? ts[2] : ts[3];
+            if (j < 4 * NQ && w < nT) {
+                atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)(ea + hg1 * nd));
+                atomicAdd(&I.dM[w], -2 * (fl - 2 * fd));
+                atomicAdd(&I.fl[t], fl);
+            }
+        } else {
             for (int i = 0; i < 4; ++i) {
                 const int w = 4 * q + i;
-                if (w >= nT) break;
-                const int fl = (int)((ty.flips >> (8 * i)) & 0xFFu), fd = (int)((ty.fdown >> (8 * i)) & 0xFFu);
-                const int nd = (int)((ty.nd >> (8 * i)) & 0xFFu);
-                // dEJ collects minus the new E_J (all threads of the quad add);
-                // Gaussian couplings: the tallies summed s' (S_u + hgrid) over
-                // this thread's 4 * items1 odd sites, so take hgrid sum s' out
-                long long sE = (long long)ty.accE[i] + nd;
-                if constexpr (JK == 0) sE -= (long long)d.hgrid * (4 * items1 - 2 * nd);
-                atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)sE);
-                atomicAdd(&I.dM[w], -2 * (fl - 2 * fd));
-                atomicAdd(&I.fl[ts[i]], fl);
+                if (w < nT) {
+                    const int fl = (int)((ty.flips >> (8 * i)) & 0xFFu), fd = (int)((ty.fdown >> (8 * i)) & 0xFFu);
+                    const int nd = (int)((ty.nd >> (8 * i)) & 0xFFu);
+                    atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)(ty.accE[i] + hg1 * nd));
+                    atomicAdd(&I.dM[w], -2 * (fl - 2 * fd));
+                    atomicAdd(&I.fl[ts[i]], fl);
+                }
             }
         }
         __syncthreads();
-        for (int i = tid; i < nT; i += T) {
-            I.EJ[i] = -I.dEJ[i];
-            I.M[i] += I.dM[i];
-            I.dEJ[i] = 0;  // cleared for the next sweep's tallies
-            I.dM[i] = 0;
-        }
-        __syncthreads();
-        exchange_pass(A, d, r, n, I, unit, hd, tm);
+        exchange_pass_e(A, d, r, n, I, energy, tm);
         __syncthreads();
         // Snapshot for the overlap measurement, in slot order.
         const int64_t done = n + 1;
@@ -329,7 +369,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
             }
             for (int t = tid; !tm.ghost && t < nT; t += T) {
                 const int w = I.was[t];
-                A.frameE[f * 2 * A.total_slots + gi + t] = (double)I.EJ[w] * unit - hd * (double)I.M[w];
+                A.frameE[f * 2 * A.total_slots + gi + t] = energy(w);
             }
             ++f;
             __syncthreads();  // the next sweep changes the spins read here
@@ -346,8 +386,8 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     }
     for (int i = tid; !tm.ghost && i < nT; i += T) {
         A.was[gi + i] = I.was[i];
-        A.EJ[gi + i] = I.EJ[i];
-        A.M[gi + i] = I.M[i];
+        A.EJ[gi + i] = -I.dEJ[i];
+        A.M[gi + i] = I.M[i] + I.dM[i];
         A.flips[gi + i] += I.fl[i];
         A.swaps[gi + i] += I.sw[i];
     }

@@ -151,22 +151,21 @@ __device__ __forceinline__ ItemLds item_lds(char *smem, int L, int nT, int jkind
 
 // Replica exchange of neighbouring slots (t, t+1), t = n&1, n&1 + 2, ...
 // (Methods: parallel tempering; even-odd pairs alternate with the sweep
-// parity).  D = (beta_t - beta_{t+1}) (E_t - E_{t+1}) in binary64; accepted
-// iff D >= 0 or u53 < exp_ea64(D), the uniform from the exchange counter
-// (0, n, (1 << 28) | (t << 1) | r, sample).  Swaps walker labels only, in
-// both maps (was: slot -> walker, sow: walker -> slot), so the sweep that
-// follows reads its temperatures without rebuilding sow.
-__device__ __forceinline__ void exchange_pass(const SweepArgs &A, const SampleDev &d, int r, int64_t n,
-                                              const ItemLds &I, double unit, double hd, const Team tm = whole_block())
+// parity).  D = (beta_t - beta_{t+1}) (E_t - E_{t+1}) in binary64, E_w =
+// energy(w); accepted iff D >= 0 or u53 < exp_ea64(D), the uniform from the
+// exchange counter (0, n, (1 << 28) | (t << 1) | r, sample).  Swaps walker
+// labels only, in both maps (was: slot -> walker, sow: walker -> slot), so the
+// sweep that follows reads its temperatures without rebuilding sow.
+template <class Energy>
+__device__ __forceinline__ void exchange_pass_e(const SweepArgs &A, const SampleDev &d, int r, int64_t n,
+                                                const ItemLds &I, Energy energy, const Team tm)
 {
     const int nT = d.n_T, T = tm.T;
     for (int j = tm.tid;; j += T) {
         const int t = (int)(n & 1) + 2 * j;
         if (t + 1 >= nT) break;
         const int w0 = I.was[t], w1 = I.was[t + 1];
-        const double E0 = (double)I.EJ[w0] * unit - hd * (double)I.M[w0];
-        const double E1 = (double)I.EJ[w1] * unit - hd * (double)I.M[w1];
-        const double D = (I.b64[t] - I.b64[t + 1]) * (E0 - E1);
+        const double D = (I.b64[t] - I.b64[t + 1]) * (energy(w0) - energy(w1));
         bool acc = D >= 0.0;
         if (!acc) {
             const u32x4 q = philox4x32_10(0u, (uint32_t)n,
@@ -182,6 +181,42 @@ __device__ __forceinline__ void exchange_pass(const SweepArgs &A, const SampleDe
             I.sw[t] += 1;
         }
     }
+}
+
+// The same with E_w = EJ_w unit - h M_w from the walker arrays.
+__device__ __forceinline__ void exchange_pass(const SweepArgs &A, const SampleDev &d, int r, int64_t n,
+                                              const ItemLds &I, double unit, double hd, const Team tm = whole_block())
+{
+    exchange_pass_e(
+        A, d, r, n, I, [&](int w) { return (double)I.EJ[w] * unit - hd * (double)I.M[w]; }, tm);
+}
+
+// v of the lane K places along in the same row of 16 lanes (rotation).
+template <int K>
+__device__ __forceinline__ int row_rotate(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x120 + K, 0xF, 0xF, true);
+}
+
+template <int K>
+__device__ __forceinline__ long long row_rotate(long long v)
+{
+    const unsigned lo = (unsigned)row_rotate<K>((int)(unsigned long long)v);
+    const unsigned hi = (unsigned)row_rotate<K>((int)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Sum of v over the lanes of this lane's row of 16 whose index agrees with
+// this lane's modulo S (S = 1, 2, 4, 8 or 16, uniform): rotations by S, 2S,
+// .., 8.  Every lane of the wave must be active.
+template <class V>
+__device__ __forceinline__ V row_residue_sum(V v, int S)
+{
+    if (S <= 1) v += row_rotate<1>(v);
+    if (S <= 2) v += row_rotate<2>(v);
+    if (S <= 4) v += row_rotate<4>(v);
+    if (S <= 8) v += row_rotate<8>(v);
+    return v;
 }
 
 }  // namespace ea

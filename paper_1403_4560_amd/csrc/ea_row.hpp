@@ -342,7 +342,8 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
     for (int i = tid; i < nT; i += T) {
         I.was[i] = A.was[gi + i];
         I.sow[A.was[gi + i]] = i;  // kept by exchange_pass from here on
-        I.dEJ[i] = 0;
+        // row engine: E_J = -dEJ (see the sweep loop); site engine: EJ + dEJ
+        I.dEJ[i] = ROW ? -A.EJ[gi + i] : 0;
         I.dM[i] = 0;
         I.EJ[i] = A.EJ[gi + i];
         I.M[i] = A.M[gi + i];
@@ -371,11 +372,31 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
     const double unit = JK == 0 ? 0x1p-18 : 1.0;
     const double hd = (double)d.h32;
     const int64_t n0 = A.state[0];
-    int64_t next_meas = next_measurement(n0, A.measure_every, A.measure_start);
+    // (the period from an opaque copy: the division's set-up is then made
+    // here, per item, rather than hoisted out of the item loop of a
+    // persistent kernel and held in registers across it, which spills)
+    int32_t every = A.measure_every;
+    asm volatile("" : "+s"(every));
+    int64_t next_meas = next_measurement(n0, every, A.measure_start);
     int64_t f = 0;  // frame of the next measurement within this chunk
+    // Energy of walker w after a sweep.  Row engine: the second half-sweep's
+    // tallies leave minus E_J in dEJ and the magnetisation change in dM; both
+    // are folded in at the start of the next sweep, before its own tallies
+    // (which follow the first half-sweep's barrier), so no pass of their own
+    // is needed.  Site engine: a pass after the sweep folds them in.
+    const auto energy = [&](int w) {
+        return ROW ? (double)(-I.dEJ[w]) * unit - hd * (double)(I.M[w] + I.dM[w])
+                   : (double)I.EJ[w] * unit - hd * (double)I.M[w];
+    };
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
         if constexpr (ROW) {
+            #pragma unroll 1
+            for (int i = tid; i < nT; i += T) {
+                I.M[i] += I.dM[i];
+                I.dM[i] = 0;
+                I.dEJ[i] = 0;
+            }
             // Barriers stay outside the walker test: a wave may hold lanes of
             // an active and an idle walker.  A walker's CPW lanes in a wave are
             // aligned and all active or all idle, so the group sums see only
@@ -410,14 +431,16 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
             site_half_sweep<L, JK>(A, d, r, 1, n, I, tm);
         }
         __syncthreads();
-        for (int i = tid; i < nT; i += T) {
-            I.EJ[i] = ROW ? -I.dEJ[i] : I.EJ[i] + I.dEJ[i];
-            I.M[i] += I.dM[i];
-            I.dEJ[i] = 0;  // cleared for the next sweep's tallies
-            I.dM[i] = 0;
+        if constexpr (!ROW) {
+            for (int i = tid; i < nT; i += T) {
+                I.EJ[i] += I.dEJ[i];
+                I.M[i] += I.dM[i];
+                I.dEJ[i] = 0;  // cleared for the next sweep's tallies
+                I.dM[i] = 0;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        exchange_pass(A, d, r, n, I, unit, hd, tm);
+        exchange_pass_e(A, d, r, n, I, energy, tm);
         __syncthreads();
         // Snapshot for the overlap measurement, in slot order.
         const int64_t done = n + 1;
@@ -430,7 +453,7 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
             }
             for (int t = tid; !tm.ghost && t < nT; t += T) {
                 const int w = I.was[t];
-                A.frameE[f * 2 * A.total_slots + gi + t] = (double)I.EJ[w] * unit - hd * (double)I.M[w];
+                A.frameE[f * 2 * A.total_slots + gi + t] = energy(w);
             }
             ++f;
             __syncthreads();  // the next sweep changes the spins read here
@@ -446,8 +469,8 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
     if (!tw.ghost) copy_walkers(I.S, item_walker_stride(L), A.spins + sbase, nT, N, false, tw);
     for (int i = tw.tid; !tw.ghost && i < nT; i += T) {
         A.was[gi + i] = I.was[i];
-        A.EJ[gi + i] = I.EJ[i];
-        A.M[gi + i] = I.M[i];
+        A.EJ[gi + i] = ROW ? -I.dEJ[i] : I.EJ[i];
+        A.M[gi + i] = ROW ? I.M[i] + I.dM[i] : I.M[i];
         A.flips[gi + i] += I.fl[i];
         A.swaps[gi + i] += I.sw[i];
     }
