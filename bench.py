@@ -88,8 +88,8 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the factors a plain copy of
 # known size reads), keyed by a fingerprint of the kernel sources they were
 # taken on; reported as null once the kernels change.
-MEASURED_TRAFFIC = {"L16_gauss": ("2079493e10d59eae", 2.0324e9), "L32_pm1": ("2079493e10d59eae", 3.5385e9),
-                    "mixed_L6_12": ("2079493e10d59eae", 0.7663e9)}
+MEASURED_TRAFFIC = {"L16_gauss": ("5e0c792edf339ffc", 2.0324e9), "L32_pm1": ("5e0c792edf339ffc", 3.5390e9),
+                    "mixed_L6_12": ("5e0c792edf339ffc", 0.7666e9), "L8_gauss": ("5e0c792edf339ffc", 0.1367e9)}
 KERNEL_SOURCES = tuple("paper_1403_4560_amd/csrc/" + f for f in (
     "ea_kernels.hip", "ea_bits.hip", "ea_group.hip", "ea_batch.hip", "ea_row.hpp", "ea_group.hpp", "ea_item.hpp",
     "ea_update.hpp", "ea_device.hpp", "ea_types.hpp"))
@@ -175,15 +175,17 @@ def measured_peak_tops(mix, peaks):
     return n / t / 1e12
 
 
-def time_workload(binding, work, stream, steps, warmup, tier=0, timing_steps=3, autotune=True):
+def time_workload(binding, work, stream, steps, warmup, tier=0, timing_steps=3, autotune=True, batch=None):
     """Graph-replayed steps timed by the host clock (the production path), then
     an untimed pass of direct launches with HIP events around the sweep
     kernels of every chunk, for the roofline.  The plan is autotuned first
-    (outside the timed region)."""
+    (outside the timed region); batch=False then runs every lattice-size class
+    in a launch of its own (per-class kernel counters)."""
     import torch
     ens = binding.Ensemble(work, stream=stream.cuda_stream, tier=tier)
     plan = ens.autotune(trial_sweeps=4) if autotune else ens.get_plan()
-    ens.set_plan(chunk=SWEEPS_PER_STEP, use_graph=True)
+    ens.set_plan(chunk=SWEEPS_PER_STEP, use_graph=True, batch=batch)
+    plan = ens.get_plan()
     bplan = ens.batch_plan()
     for _ in range(warmup):
         ens.sweep_pt(SWEEPS_PER_STEP)  # the first call captures the chunk's graph
@@ -205,8 +207,12 @@ def time_workload(binding, work, stream, steps, warmup, tier=0, timing_steps=3, 
     engines = sorted(set(ens.engines()))
     ens.close()
     assert bad == 0, "incremental energies diverged"
+    # one sweep launch per chunk: its average duration; several (class
+    # launches): their summed duration per chunk
+    per_step = max(k_launches, 1) / timing_steps
+    avg = k_ms / 1e3 / (max(k_launches, 1) if per_step <= 1 else timing_steps)
     return {"dt": dt, "ms_per_step": dt * 1e3 / steps, "direct_ms_per_step": dt_direct * 1e3 / timing_steps,
-            "avg_launch_s": k_ms / 1e3 / max(k_launches, 1), "engines": engines,
+            "avg_launch_s": avg, "sweep_launches_per_step": per_step, "engines": engines,
             "plan": {"batch_launch": bool(plan.batch), "site_threads": plan.threads,
                      "classes": [{"L": L, "engine": e, "items_per_workgroup": t}
                                  for L, e, t in zip(bplan["L"], bplan["engine"], bplan["teams"])]}}
@@ -243,7 +249,8 @@ def roofline_of(name, work, timed, tier, peaks):
     r = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
          "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
          "kernel": kernel, "avg_launch_ms": avg * 1e3,
-         "ops_per_attempt": ops, "traffic_unit": "HBM bytes per launch (hardware counters)"}
+         "ops_per_attempt": ops, "traffic_unit": "HBM bytes per launch (hardware counters)",
+         "sweep_launches_per_step": timed.get("sweep_launches_per_step", 1)}
     engine = ENGINE_OF.get(name, "group")
     if tier == 0 and peaks is not None:
         mp = measured_peak_tops(OP_MIX["bits" if engine == "bits" else "gauss"], peaks)
@@ -281,6 +288,9 @@ def main():
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the plan autotuning done before each timed workload")
+    ap.add_argument("--class-launches", action="store_true",
+                    help="after autotuning, run each lattice-size class in a launch of its own (per-class "
+                         "kernel counters of an uneven batch)")
     ap.add_argument("--tier", type=int, default=0,
                     help="0 automatic (default); 1 HBM-resident for L divisible by 8; 2 no one-bit engine; "
                          "3 one-site-per-thread engine (comparisons only)")
@@ -328,7 +338,7 @@ def main():
     progress("workload %s ready" % args.workload)
     attempts_per_step = work.attempts_per_sweep() * SWEEPS_PER_STEP
     timed = time_workload(binding, work, stream, args.steps, args.warmup, tier=args.tier,
-                          autotune=not args.no_autotune)
+                          autotune=not args.no_autotune, batch=False if args.class_launches else None)
     dt = timed["dt"]
     value = attempts_per_step * args.steps / (dt * 1e9)
     progress("timed %d graph-replayed steps in %.3f s: %.1f attempts/ns (direct launches: %.3f ms per step)"
