@@ -337,6 +337,21 @@ ea_status ea_query_engines(const ea_ensemble *ens, int32_t *engines_host);
  * device. */
 ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev);
 
+/* Check of the replica-exchange shortcut (Methods: parallel tempering; the
+ * acceptance min(1, e^D) as u53 < exp_ea64(D)).  For D < 0 the kernels decide
+ * from a = 2^y, y = fl32(D log2 e), the hardware exponential: D < -40 rejects
+ * (u53 >= 2^-53 > exp_ea64(D)) unless u53 = 0; for -40 <= D < 0,
+ * u53 < a (1 - 2^-16) accepts and u53 > a (1 + 2^-16) rejects; anything else
+ * evaluates exp_ea64.  The rounding of y moves a by at most a relative
+ * 1.32e-6 (|y| < 58, half an ulp of 2^-18); this call checks, over every
+ * binary32 y in [-58, 0] (1.1e9 values), the remaining bounds: the hardware
+ * exponential within a relative 2^-22 of 2^y and exp_ea64(y) within 2^-49 of
+ * e^y, so that a / exp_ea64(D) stays within 1 +- 1.7e-6 and both shortcuts
+ * decide as the exact test would.  *violations must be 0; *max_rel_dev is the
+ * largest relative deviation of the hardware exponential seen.  Synchronizing;
+ * uses the current device. */
+ea_status ea_verify_exchange_bracket(int64_t *violations, double *max_rel_dev);
+
 /* Microbenchmarks of the rates the kernels' rooflines are priced against, on
  * the current device (about a second; synchronizing; allocates and frees
  * 2 GiB for the copy).  rates_host[6] (caller-owned) receives, per second:

@@ -82,6 +82,7 @@ _SIGS = [
     ("ea_bind_buffers", ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_size_t]),
     ("ea_verify_exp_bracket", ctypes.c_int, [_VP, _VP]),
     ("ea_measure_peaks", ctypes.c_int, [_VP]),
+    ("ea_verify_exchange_bracket", ctypes.c_int, [_VP, _VP]),
     ("ea_destroy", None, [_VP]),
     ("ea_last_error", ctypes.c_char_p, []),
 ]
@@ -123,6 +124,15 @@ def verify_exp_bracket():
     v = ctypes.c_int64()
     m = ctypes.c_double()
     _check(load().ea_verify_exp_bracket(ctypes.byref(v), ctypes.byref(m)))
+    return v.value, m.value
+
+
+def verify_exchange_bracket():
+    """(violations, max relative deviation of the hardware exponential) of the
+    replica-exchange shortcut."""
+    v = ctypes.c_int64()
+    m = ctypes.c_double()
+    _check(load().ea_verify_exchange_bracket(ctypes.byref(v), ctypes.byref(m)))
     return v.value, m.value
 
 

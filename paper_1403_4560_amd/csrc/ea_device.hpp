@@ -146,4 +146,31 @@ __device__ __forceinline__ double u53_of(uint32_t w0, uint32_t w1)
     return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6)) * 0x1p-53;
 }
 
+// Replica-exchange test for D < 0: returns u < exp_ea64(D), u a 53-bit
+// uniform (a multiple of 2^-53 in [0, 1)), deciding from the hardware
+// exponential wherever that is safe.
+//   D < -40: exp_ea64(D) < e^-40 (1 + 2^-50) < 2^-57 < 2^-53 <= u unless u = 0.
+//   -40 <= D < 0: e = 2^y, y = fl32(D log2 e) with |t| < 58 for t = D log2 e,
+//     so |y - t| <= 2^-19 (half an ulp at |t| < 64); the hardware exp2 is
+//     within a relative 2^-22 of 2^y on y in [-58, 0] (checked on every
+//     binary32 there by ea_verify_exchange_bracket), and exp_ea64 within 2^-50
+//     of e^D.  So e / exp_ea64(D) lies within 1 +- 1.7e-6, well inside the
+//     margin 2^-16 = 1.5e-5: u < e (1 - 2^-16) implies u < exp_ea64(D), and
+//     u > e (1 + 2^-16) implies u > exp_ea64(D).  Between the two (about 3e-5
+//     of the draws), and for u = 0, exp_ea64 decides.
+constexpr double EXCHANGE_FAST_MIN = -40.0;
+constexpr double EXCHANGE_MARGIN = 0x1p-16;
+
+__device__ __forceinline__ bool exchange_accept(double u, double D)
+{
+    if (u != 0.0) {
+        if (D < EXCHANGE_FAST_MIN) return false;
+        const float y = (float)(D * __longlong_as_double(0x3FF71547652B82FEll));  // D log2(e)
+        const double e = (double)__builtin_amdgcn_exp2f(y);
+        if (u < e * (1.0 - EXCHANGE_MARGIN)) return true;
+        if (u > e * (1.0 + EXCHANGE_MARGIN)) return false;
+    }
+    return u < exp_ea64(D);
+}
+
 }  // namespace ea

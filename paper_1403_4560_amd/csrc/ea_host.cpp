@@ -35,6 +35,7 @@ __global__ void measure_all_kernel(MeasureArgs A);
 __global__ void advance_kernel(int64_t *state, int64_t k);
 template <int JK> __global__ void batch_sweep_kernel(SweepArgs A, BatchArgs B);
 __global__ void exp_bracket_kernel(uint32_t, uint32_t, unsigned long long *, unsigned int *);
+__global__ void exchange_bracket_kernel(uint32_t, uint32_t, unsigned long long *, unsigned long long *);
 template <int JK>
 __global__ void energy_kernel(const SampleDev *, const int32_t *, const int8_t *, const void *, int64_t *,
                               int32_t *);
@@ -1991,6 +1992,37 @@ ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev)
     std::memcpy(&mf, &m, sizeof mf);
     *violations = (int64_t)v;
     *max_rel_dev = (double)mf;
+    return EA_OK;
+}
+
+ea_status ea_verify_exchange_bracket(int64_t *violations, double *max_rel_dev)
+{
+    if (!violations || !max_rel_dev) return fail(EA_EINVAL, "null argument");
+    // binary32 bit patterns from -0 (0x80000000) to -58 (0xC2680000)
+    const uint32_t first = 0x80000000u, count = 0xC2680000u - 0x80000000u + 1u;
+    unsigned long long *dv = nullptr, *dm = nullptr;
+    if (hipMalloc(&dv, sizeof *dv) != hipSuccess) return fail(EA_ENOMEM, "hipMalloc failed");
+    if (hipMalloc(&dm, sizeof *dm) != hipSuccess) {
+        (void)hipFree(dv);
+        return fail(EA_ENOMEM, "hipMalloc failed");
+    }
+    hipError_t st = hipMemset(dv, 0, sizeof *dv);
+    if (st == hipSuccess) st = hipMemset(dm, 0, sizeof *dm);
+    if (st == hipSuccess) {
+        hipLaunchKernelGGL(exchange_bracket_kernel, dim3((count + 255) / 256), dim3(256), 0, nullptr, first, count,
+                           dv, dm);
+        st = hipGetLastError();
+    }
+    unsigned long long v = 0, m = 0;
+    if (st == hipSuccess) st = hipMemcpy(&v, dv, sizeof v, hipMemcpyDeviceToHost);
+    if (st == hipSuccess) st = hipMemcpy(&m, dm, sizeof m, hipMemcpyDeviceToHost);
+    (void)hipFree(dv);
+    (void)hipFree(dm);
+    if (st != hipSuccess) return fail(EA_EDEVICE, "exchange bracket check failed: %s", hipGetErrorString(st));
+    double md;
+    std::memcpy(&md, &m, sizeof md);
+    *violations = (int64_t)v;
+    *max_rel_dev = md;
     return EA_OK;
 }
 

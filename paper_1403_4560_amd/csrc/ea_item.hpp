@@ -152,10 +152,11 @@ __device__ __forceinline__ ItemLds item_lds(char *smem, int L, int nT, int jkind
 // Replica exchange of neighbouring slots (t, t+1), t = n&1, n&1 + 2, ...
 // (Methods: parallel tempering; even-odd pairs alternate with the sweep
 // parity).  D = (beta_t - beta_{t+1}) (E_t - E_{t+1}) in binary64, E_w =
-// energy(w); accepted iff D >= 0 or u53 < exp_ea64(D), the uniform from the
-// exchange counter (0, n, (1 << 28) | (t << 1) | r, sample).  Swaps walker
-// labels only, in both maps (was: slot -> walker, sow: walker -> slot), so the
-// sweep that follows reads its temperatures without rebuilding sow.
+// energy(w); accepted iff D >= 0 or u53 < exp_ea64(D) (decided by
+// exchange_accept), u53 from the exchange counter (0, n, (1 << 28) | (t << 1)
+// | r, sample).  Swaps walker labels only, in both maps (was: slot -> walker,
+// sow: walker -> slot), so the sweep that follows reads its temperatures
+// without rebuilding sow.
 template <class Energy>
 __device__ __forceinline__ void exchange_pass_e(const SweepArgs &A, const SampleDev &d, int r, int64_t n,
                                                 const ItemLds &I, Energy energy, const Team tm)
@@ -171,7 +172,7 @@ __device__ __forceinline__ void exchange_pass_e(const SweepArgs &A, const Sample
             const u32x4 q = philox4x32_10(0u, (uint32_t)n,
                                           (PURPOSE_EXCHANGE << 28) | ((uint32_t)t << 1) | (uint32_t)r,
                                           d.sample_id, A.key0, A.key1);
-            acc = u53_of(q.x, q.y) < exp_ea64(D);
+            acc = exchange_accept(u53_of(q.x, q.y), D);
         }
         if (acc) {
             I.was[t] = w1;

@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(64) hbm_exchange_kernel(SweepArgs A)
             const u32x4 q = philox4x32_10(0u, (uint32_t)n,
                                           (PURPOSE_EXCHANGE << 28) | ((uint32_t)t << 1) | (uint32_t)r,
                                           d.sample_id, A.key0, A.key1);
-            acc = u53_of(q.x, q.y) < exp_ea64(D);
+            acc = exchange_accept(u53_of(q.x, q.y), D);
         }
         if (acc) {
             A.was[gi + t] = w1;
@@ -579,6 +579,23 @@ __global__ void exp_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned
             atomicMax(max_dev_bits, __float_as_uint(dev));
         }
     }
+    if (!ok) atomicAdd(violations, 1ull);
+}
+
+// The replica-exchange shortcut (exchange_accept in ea_device.hpp), one
+// thread per binary32 bit pattern y from -0 down to -58: the hardware
+// exponential lies within a relative 2^-22 of 2^y (binary64 exp2 as the
+// reference) and exp_ea64(y) within 2^-49 of e^y (binary64 exp, itself within
+// an ulp); records the largest |2^y (hardware) / 2^y - 1|.
+__global__ void exchange_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned long long *violations,
+                                        unsigned long long *max_dev_bits)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float y = __uint_as_float(first_bits + i);
+    const double dev = fabs((double)__builtin_amdgcn_exp2f(y) / exp2((double)y) - 1.0);
+    const bool ok = dev <= 0x1p-22 && fabs(exp_ea64((double)y) / exp((double)y) - 1.0) <= 0x1p-49;
+    atomicMax(max_dev_bits, (unsigned long long)__double_as_longlong(dev));
     if (!ok) atomicAdd(violations, 1ull);
 }
 

@@ -472,6 +472,18 @@ def test_fast_exponential_bracket_is_exhaustively_safe(torch_cuda):
     assert dev < 2.0 ** -13
 
 
+def test_exchange_shortcut_is_exhaustively_safe(torch_cuda):
+    # the exchange test decides u53 < exp_ea64(D) from the hardware exponential
+    # outside a relative margin of 2^-16; with the rounding of its argument
+    # (1.32e-6) the bounds checked here keep it inside 1.7e-6
+    from paper_1403_4560_amd import binding
+    v, dev = binding.verify_exchange_bracket()
+    print("exchange bracket: violations=%d max relative deviation=%.3g" % (v, dev), flush=True)
+    assert v == 0
+    assert dev <= 2.0 ** -22
+    assert 2.0 ** -19 * math.log(2.0) * 1.001 + dev + 2.0 ** -49 < 1.7e-6 < 2.0 ** -16
+
+
 def test_autotune_keeps_results(torch_cuda, monkeypatch):
     from paper_1403_4560_amd import binding
     monkeypatch.delenv("EA_TUNE_CACHE", raising=False)
