@@ -88,8 +88,8 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the factors a plain copy of
 # known size reads), keyed by a fingerprint of the kernel sources they were
 # taken on; reported as null once the kernels change.
-MEASURED_TRAFFIC = {"L16_gauss": ("5e0c792edf339ffc", 2.0324e9), "L32_pm1": ("5e0c792edf339ffc", 3.5390e9),
-                    "mixed_L6_12": ("5e0c792edf339ffc", 0.7666e9), "L8_gauss": ("5e0c792edf339ffc", 0.1367e9)}
+MEASURED_TRAFFIC = {"L16_gauss": ("c84b29870b23fe6d", 2.0324e9), "L32_pm1": ("c84b29870b23fe6d", 3.5387e9),
+                    "mixed_L6_12": ("c84b29870b23fe6d", 0.7669e9), "L8_gauss": ("c84b29870b23fe6d", 0.1367e9)}
 KERNEL_SOURCES = tuple("paper_1403_4560_amd/csrc/" + f for f in (
     "ea_kernels.hip", "ea_bits.hip", "ea_group.hip", "ea_batch.hip", "ea_row.hpp", "ea_group.hpp", "ea_item.hpp",
     "ea_update.hpp", "ea_device.hpp", "ea_types.hpp"))

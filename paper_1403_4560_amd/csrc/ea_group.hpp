@@ -253,7 +253,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     const auto energy = [&](int w) { return (double)(-I.dEJ[w]) * unit - hd * (double)(I.M[w] + I.dM[w]); };
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
-        #pragma unroll 1
+#pragma unroll 1
         for (int i = tid; i < nT; i += T) {
             I.M[i] += I.dM[i];
             I.dM[i] = 0;

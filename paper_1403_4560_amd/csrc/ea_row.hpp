@@ -391,7 +391,7 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
     for (int it = 0; it < A.K; ++it) {
         const int64_t n = n0 + it;
         if constexpr (ROW) {
-            #pragma unroll 1
+#pragma unroll 1
             for (int i = tid; i < nT; i += T) {
                 I.M[i] += I.dM[i];
                 I.dM[i] = 0;
