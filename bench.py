@@ -207,12 +207,10 @@ def time_workload(binding, work, stream, steps, warmup, tier=0, timing_steps=3, 
     engines = sorted(set(ens.engines()))
     ens.close()
     assert bad == 0, "incremental energies diverged"
-    # one sweep launch per chunk: its average duration; several (class
-    # launches): their summed duration per chunk
-    per_step = max(k_launches, 1) / timing_steps
-    avg = k_ms / 1e3 / (max(k_launches, 1) if per_step <= 1 else timing_steps)
+    # the events bracket the sweep kernels of each chunk: one launch, or with
+    # class launches all of them (their summed time per chunk)
     return {"dt": dt, "ms_per_step": dt * 1e3 / steps, "direct_ms_per_step": dt_direct * 1e3 / timing_steps,
-            "avg_launch_s": avg, "sweep_launches_per_step": per_step, "engines": engines,
+            "avg_launch_s": k_ms / 1e3 / max(k_launches, 1), "engines": engines,
             "plan": {"batch_launch": bool(plan.batch), "site_threads": plan.threads,
                      "classes": [{"L": L, "engine": e, "items_per_workgroup": t}
                                  for L, e, t in zip(bplan["L"], bplan["engine"], bplan["teams"])]}}
@@ -249,8 +247,7 @@ def roofline_of(name, work, timed, tier, peaks):
     r = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
          "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
          "kernel": kernel, "avg_launch_ms": avg * 1e3,
-         "ops_per_attempt": ops, "traffic_unit": "HBM bytes per launch (hardware counters)",
-         "sweep_launches_per_step": timed.get("sweep_launches_per_step", 1)}
+         "ops_per_attempt": ops, "traffic_unit": "HBM bytes per launch (hardware counters)"}
     engine = ENGINE_OF.get(name, "group")
     if tier == 0 and peaks is not None:
         mp = measured_peak_tops(OP_MIX["bits" if engine == "bits" else "gauss"], peaks)

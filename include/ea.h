@@ -272,10 +272,11 @@ ea_status ea_get_batch_plan(const ea_ensemble *ens, int32_t *n_classes, int32_t 
  * unchanged; only the launch shape is.  Synchronizing. */
 ea_status ea_set_batch_plan(ea_ensemble *ens, const int32_t *teams);
 
-/* Kernel timing on the bound stream: when enabled, every sweep-kernel launch
- * is bracketed by HIP events; ea_kernel_time returns the summed duration in
- * milliseconds and the number of launches since it was enabled (it
- * synchronizes).  Graph replay is bypassed while timing is on. */
+/* Kernel timing on the bound stream: when enabled, the sweep kernels of every
+ * chunk (one launch, or one per launch class; the measurement launch
+ * excluded) are bracketed by a pair of HIP events; ea_kernel_time returns the
+ * summed duration in milliseconds and the number of chunks timed since it was
+ * enabled (it synchronizes).  Graph replay is bypassed while timing is on. */
 ea_status ea_set_timing(ea_ensemble *ens, int32_t enable);
 ea_status ea_kernel_time(ea_ensemble *ens, double *ms_total, int64_t *launches);
 
