@@ -439,6 +439,27 @@ def test_full_mixed_workload_sampled(torch_cuda):
     assert_same(work, st, ms, ref, samples=pick)
 
 
+@pytest.mark.parametrize("name,pick", [("L16_gauss", [1, 1024, 2046]),
+                                       ("mixed_L6_12", [2, 7, 4093, 4088, 1029, 2051])])
+def test_full_workload_in_the_bench_plan(torch_cuda, name, pick):
+    """The whole batch exactly as bench.py times it: autotuned plan, chunks of
+    100 sweeps replayed from a hipGraph, measurements from the first sweep;
+    200 sweeps, samples spread over the batch compared with the oracle."""
+    from paper_1403_4560_amd import binding
+    work = W.config_workload(name, measure_start=0)
+    sweeps = 200
+    print("case: %s whole batch in the bench plan, %d sweeps" % (name, sweeps), flush=True)
+    with binding.Ensemble(work) as ens:
+        ens.autotune(trial_sweeps=2)
+        ens.set_plan(chunk=100, use_graph=True)
+        ens.sweep_pt(sweeps)
+        st = ens.read_state()
+        ms = ens.measure()
+        assert ens.check_energies() == 0
+    ref = O.OracleEnsemble(work.subset(pick)).run(sweeps)
+    assert_same(work, st, ms, ref, samples=pick)
+
+
 def test_L16_long_run_in_the_bench_plan(torch_cuda):
     """Two L = 16 samples for 600 sweeps in the benchmark's plan (chunks of 100
     replayed from a hipGraph), measuring every 10 sweeps from 300: spins,
