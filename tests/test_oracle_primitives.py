@@ -89,3 +89,23 @@ def test_exp_ea64_special_values():
     assert O.exp_ea64(0.0) == 1.0
     assert O.exp_ea64(-700.0) > 0.0
     assert O.exp_ea64(-700.0000001) == 0.0
+
+
+def test_exchange_shortcut_bounds():
+    # The kernels' exchange test (u53 < exp_ea64(D), D < 0) rejects outright
+    # below D = -40 and otherwise compares u53 with the hardware 2^y,
+    # y = fl32(D log2 e), widened by a relative 2^-16.  The bounds it rests on:
+    # exp_ea64 below -40 is under the smallest positive 53-bit uniform ...
+    assert O.exp_ea64(-40.0) < 2.0 ** -57 < 2.0 ** -53
+    xs = -40.0 - np.random.default_rng(3).random(1000) * 700.0
+    assert (O.exp_ea64_n(xs) < 2.0 ** -57).all()
+    # ... rounding D log2 e (|.| < 58) to binary32 moves y by at most 2^-19 ...
+    rng = np.random.default_rng(4)
+    D = -rng.random(100000) * 40.0
+    t = D * 1.4426950408889634
+    y = t.astype(np.float32).astype(np.float64)
+    assert np.abs(y - t).max() <= 2.0 ** -19
+    # ... so with the hardware exponential within 2^-22 of 2^y (checked on every
+    # binary32 by ea_verify_exchange_bracket) and exp_ea64 within 2^-49 of e^D,
+    # the estimate stays well inside the margin
+    assert (2.0 ** (2.0 ** -19) - 1.0) * 1.0001 + 2.0 ** -22 + 2.0 ** -49 < 1.7e-6 < 2.0 ** -16
