@@ -348,9 +348,11 @@ ea_status ea_verify_exp_bracket(int64_t *violations, double *max_rel_dev);
  * binary32 y in [-58, 0] (1.1e9 values), the remaining bounds: the hardware
  * exponential within a relative 2^-22 of 2^y and exp_ea64(y) within 2^-49 of
  * e^y, so that a / exp_ea64(D) stays within 1 +- 1.7e-6 and both shortcuts
- * decide as the exact test would.  *violations must be 0; *max_rel_dev is the
- * largest relative deviation of the hardware exponential seen.  Synchronizing;
- * uses the current device. */
+ * decide as the exact test would; it also compares the kernels' decision with
+ * the exact test for D = 1.5 y (down to -87) at uniforms spread across the
+ * margin, at u = 0 and at the largest u.  *violations must be 0;
+ * *max_rel_dev is the largest relative deviation of the hardware exponential
+ * seen.  Synchronizing; uses the current device. */
 ea_status ea_verify_exchange_bracket(int64_t *violations, double *max_rel_dev);
 
 /* Microbenchmarks of the rates the kernels' rooflines are priced against, on

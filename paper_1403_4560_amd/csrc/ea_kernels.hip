@@ -586,7 +586,11 @@ __global__ void exp_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned
 // thread per binary32 bit pattern y from -0 down to -58: the hardware
 // exponential lies within a relative 2^-22 of 2^y (binary64 exp2 as the
 // reference) and exp_ea64(y) within 2^-49 of e^y (binary64 exp, itself within
-// an ulp); records the largest |2^y (hardware) / 2^y - 1|.
+// an ulp); records the largest |2^y (hardware) / 2^y - 1|.  With D = 1.5 y
+// (down to -87, past the cut at -40) it also compares the decision itself
+// with u < exp_ea64(D) for uniforms on the 2^-53 grid at relative distances
+// k 2^-17 (k = -6 .. 6) from exp_ea64(D), both sides of the margin, and for
+// u = 0 and u = 1 - 2^-53.
 __global__ void exchange_bracket_kernel(uint32_t first_bits, uint32_t count, unsigned long long *violations,
                                         unsigned long long *max_dev_bits)
 {
@@ -594,7 +598,15 @@ __global__ void exchange_bracket_kernel(uint32_t first_bits, uint32_t count, uns
     if (i >= count) return;
     const float y = __uint_as_float(first_bits + i);
     const double dev = fabs((double)__builtin_amdgcn_exp2f(y) / exp2((double)y) - 1.0);
-    const bool ok = dev <= 0x1p-22 && fabs(exp_ea64((double)y) / exp((double)y) - 1.0) <= 0x1p-49;
+    bool ok = dev <= 0x1p-22 && fabs(exp_ea64((double)y) / exp((double)y) - 1.0) <= 0x1p-49;
+    if (y < 0.0f) {
+        const double D = 1.5 * (double)y, E = exp_ea64(D);
+        ok = ok && exchange_accept(0.0, D) == (0.0 < E) && exchange_accept(1.0 - 0x1p-53, D) == (1.0 - 0x1p-53 < E);
+        for (int k = -6; k <= 6; ++k) {
+            const double u = fmin(floor(E * (1.0 + k * 0x1p-17) * 0x1p53) * 0x1p-53, 1.0 - 0x1p-53);
+            ok = ok && exchange_accept(u, D) == (u < E);
+        }
+    }
     atomicMax(max_dev_bits, (unsigned long long)__double_as_longlong(dev));
     if (!ok) atomicAdd(violations, 1ull);
 }
