@@ -162,10 +162,14 @@ ea_status ea_read_state(ea_ensemble *ens, int8_t *spins_host, int32_t *walker_at
                         double *E_host, int64_t *sweep);
 
 /* Replace the state (resume from a checkpoint): spins in slot order as
- * returned by ea_read_state, and the sweep counter.  Energies are recomputed
- * on the device; walkers are renumbered so walker t sits at slot t, which
- * changes no later result.  Accumulators and counters are left alone. */
-ea_status ea_write_state(ea_ensemble *ens, const int8_t *spins_host, int64_t sweep);
+ * returned by ea_read_state ([S][2][n_T][N], host, copied), the walker at
+ * each slot as returned by ea_read_state ([S][2][n_T], each chain's entries a
+ * permutation of 0 .. n_T-1; EA_EINVAL otherwise), or NULL to put walker t at
+ * slot t (walker labels never change a later result: random numbers are
+ * keyed by slot), and the sweep counter.  Energies and magnetisations are
+ * recomputed on the device.  Accumulators and counters are left alone.
+ * Synchronizing. */
+ea_status ea_write_state(ea_ensemble *ens, const int8_t *spins_host, const int32_t *walker_at_slot, int64_t sweep);
 
 /* Load accumulators and counters (any NULL is left alone); layouts as in
  * ea_measure. */

@@ -61,7 +61,7 @@ _SIGS = [
     ("ea_sweep_pt_unbatched", ctypes.c_int, [_VP, _I64]),
     ("ea_measure", ctypes.c_int, [_VP, _I32, _VP, _VP, _VP]),
     ("ea_read_state", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
-    ("ea_write_state", ctypes.c_int, [_VP, _VP, _I64]),
+    ("ea_write_state", ctypes.c_int, [_VP, _VP, _VP, _I64]),
     ("ea_load_accumulators", ctypes.c_int, [_VP, _VP, _VP, _VP]),
     ("ea_reset_accumulators", ctypes.c_int, [_VP]),
     ("ea_check_energies", ctypes.c_int, [_VP, _VP]),
@@ -256,10 +256,16 @@ class Ensemble:
             "sweep": sweep.value,
         }
 
-    def write_state(self, spins_per_sample, sweep: int):
+    def write_state(self, spins_per_sample, sweep: int, walker_at_slot=None):
+        """Resume: spins in slot order and, optionally, the walker at each
+        slot (both as read_state returns them; None numbers walker t at slot t)."""
         flat = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.int8).ravel()
                                                     for x in spins_per_sample]))
-        _check(load().ea_write_state(self._h, _p(flat), int(sweep)))
+        wat = None
+        if walker_at_slot is not None:
+            wat = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.int32).ravel()
+                                                       for x in walker_at_slot]))
+        _check(load().ea_write_state(self._h, _p(flat), None if wat is None else _p(wat), int(sweep)))
 
     def load_accumulators(self, acc=None, flips=None, swaps=None):
         def cat(xs, dt):

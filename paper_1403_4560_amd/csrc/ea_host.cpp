@@ -1514,30 +1514,43 @@ ea_status ea_read_state(ea_ensemble *e, int8_t *spins_out, int32_t *was_out, dou
     return EA_OK;
 }
 
-ea_status ea_write_state(ea_ensemble *e, const int8_t *spins_in, int64_t sweep)
+ea_status ea_write_state(ea_ensemble *e, const int8_t *spins_in, const int32_t *walker_at_slot, int64_t sweep)
 {
     if (!usable(e)) return EA_ESTATE;
     if (!spins_in) return fail(EA_EINVAL, "spins is NULL");
     if (sweep < 0 || sweep > ((int64_t)1 << 31) - 1) return fail(EA_EINVAL, "sweep out of range");
     std::vector<int8_t> sp(e->spin_bytes);
-    std::vector<int32_t> was(2 * e->total_slots);
+    std::vector<int32_t> was(2 * e->total_slots), sow(2 * e->total_slots);
+    std::vector<char> seen;
     for (int s = 0; s < e->S; ++s) {
         const SampleHost &h = e->smp[s];
         const int N = h.N, HALF = N / 2;
-        for (int rw = 0; rw < 2 * h.nT; ++rw) {
-            const int8_t *src = spins_in + h.spin_off + (size_t)rw * N;
-            int8_t *dst = sp.data() + h.spin_off + (size_t)rw * N;
-            for (int i = 0; i < N; ++i) {
-                if (src[i] != 1 && src[i] != -1) return fail(EA_EINVAL, "sample %d: spin not +-1", s);
-                dst[parity(h.L, i) * HALF + (i >> 1)] = src[i];
+        for (int r = 0; r < 2; ++r) {
+            // the walker at each slot of chain r, checked to be a permutation
+            const size_t base = 2 * (size_t)h.slot_off + (size_t)r * h.nT;
+            seen.assign(h.nT, 0);
+            for (int t = 0; t < h.nT; ++t) {
+                const int w = walker_at_slot ? walker_at_slot[base + t] : t;
+                if (w < 0 || w >= h.nT || seen[w])
+                    return fail(EA_EINVAL, "sample %d chain %d: walker_at_slot is not a permutation", s, r);
+                seen[w] = 1;
+                was[base + t] = w;
+                sow[base + w] = t;
+            }
+            // slot t's spins (natural site order) become walker was[t]'s, sublattice-split
+            for (int t = 0; t < h.nT; ++t) {
+                const int8_t *src = spins_in + h.spin_off + ((size_t)r * h.nT + t) * N;
+                int8_t *dst = sp.data() + h.spin_off + ((size_t)r * h.nT + was[base + t]) * N;
+                for (int i = 0; i < N; ++i) {
+                    if (src[i] != 1 && src[i] != -1) return fail(EA_EINVAL, "sample %d: spin not +-1", s);
+                    dst[parity(h.L, i) * HALF + (i >> 1)] = src[i];
+                }
             }
         }
-        for (int r = 0; r < 2; ++r)
-            for (int t = 0; t < h.nT; ++t) was[2 * (size_t)h.slot_off + r * h.nT + t] = t;
     }
     HIP_TRY(e, hipMemcpyAsync(e->spins.p, sp.data(), e->spin_bytes, hipMemcpyHostToDevice, e->stream));
     HIP_TRY(e, hipMemcpyAsync(e->was.p, was.data(), e->was.bytes, hipMemcpyHostToDevice, e->stream));
-    HIP_TRY(e, hipMemcpyAsync(e->sow.p, was.data(), e->sow.bytes, hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(e->sow.p, sow.data(), e->sow.bytes, hipMemcpyHostToDevice, e->stream));
     int64_t sw = sweep;
     HIP_TRY(e, hipMemcpyAsync(e->state.p, &sw, sizeof sw, hipMemcpyHostToDevice, e->stream));
     if (e->jkind == EA_J_GAUSS_F32)

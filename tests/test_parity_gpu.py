@@ -211,27 +211,52 @@ def _resume_cases():
                             name="bits+group pm1 resume")]
 
 
+@pytest.mark.parametrize("with_map", [True, False])
 @pytest.mark.parametrize("case", range(3))
-def test_checkpoint_resume(torch_cuda, case):
+def test_checkpoint_resume(torch_cuda, case, with_map):
+    # with the walker map the resumed run continues the interrupted one exactly,
+    # walker labels included; without it walkers are renumbered by slot, which
+    # changes nothing else (random numbers are keyed by slot)
     from paper_1403_4560_amd import binding
     work = _resume_cases()[case]
-    print("case:", work.name, flush=True)
+    print("case:", work.name, "walker map" if with_map else "no walker map", flush=True)
     st_full, ms_full, _ = gpu_run(work, 80)
     with binding.Ensemble(work) as a:
         a.sweep_pt(35)
         st = a.read_state()
         ms = a.measure()
+    assert any((np.asarray(w) != np.arange(w.shape[1])).any() for w in st["walker_at_slot"])
     with binding.Ensemble(work) as b:
-        b.write_state(st["spins"], st["sweep"])
+        b.write_state(st["spins"], st["sweep"], walker_at_slot=st["walker_at_slot"] if with_map else None)
         b.load_accumulators(ms["acc"], ms["flips"], ms["swaps"])
         b.sweep_pt(45)
         st2 = b.read_state()
         ms2 = b.measure()
+        assert b.check_energies() == 0
     for s in range(work.n_samples):
         assert np.array_equal(st2["spins"][s], st_full["spins"][s])
         assert np.array_equal(st2["E"][s], st_full["E"][s])
         assert np.array_equal(ms2["acc"][s], ms_full["acc"][s])
+        assert np.array_equal(ms2["flips"][s], ms_full["flips"][s])
         assert np.array_equal(ms2["swaps"][s], ms_full["swaps"][s])
+        if with_map:
+            assert np.array_equal(st2["walker_at_slot"][s], st_full["walker_at_slot"][s])
+
+
+def test_write_state_rejects_a_walker_map_that_is_not_a_permutation(torch_cuda):
+    from paper_1403_4560_amd import binding
+    work = W.make_workload([4, 6], [3, 5], (0.5, 2.0), 0.2, name="bad map")
+    with binding.Ensemble(work) as ens:
+        st = ens.read_state()
+        bad = [w.copy() for w in st["walker_at_slot"]]
+        bad[1][0, 1] = bad[1][0, 0]
+        with pytest.raises(binding.EAError):
+            ens.write_state(st["spins"], st["sweep"], walker_at_slot=bad)
+        bad[1][0, 1] = 5
+        with pytest.raises(binding.EAError):
+            ens.write_state(st["spins"], st["sweep"], walker_at_slot=bad)
+        ens.write_state(st["spins"], st["sweep"], walker_at_slot=st["walker_at_slot"])
+        assert ens.check_energies() == 0
 
 
 def test_measure_now_matches_oracle(torch_cuda):
