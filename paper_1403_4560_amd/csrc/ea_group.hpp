@@ -234,9 +234,34 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
     }
     __syncthreads();
 
-    // thread -> (quad, first site group); threads beyond NQ * TPQ stay idle
+    // thread -> (quad, first site group); threads beyond NQ * TPQ stay idle.
+    // A team of eight waves holds two per SIMD (waves w and w + 4 share one;
+    // the order of the four SIMDs varies by workgroup).  When the site groups
+    // do not divide evenly (L = 12: 864 items on 512 threads, five and a half
+    // waves take two groups per half-sweep), those waves are placed by SIMD:
+    // both waves of SIMDs 2p and 2p+1 and one wave of each other SIMD, p the
+    // parity of blockIdx / 256 (the two workgroups of a CU start 256 blocks
+    // apart), so that together the two load the CU's four SIMDs evenly.  The
+    // SIMD of each wave is read from the HW_ID register and exchanged through
+    // the frame's EJ array, which this engine does not otherwise use (at least
+    // 32 bytes).  Results do not depend on the placement.
+    int vt = tid;
+    if (T == 512 && 64 % NQ == 0) {
+        int *wave_simd = (int *)(smem + o.EJ);
+        if ((tid & 63) == 0) wave_simd[tid >> 6] = (int)__builtin_amdgcn_s_getreg((1 << 11) | (4 << 6) | 4) & 3;
+        __syncthreads();
+        int n_on[4] = {0, 0, 0, 0};
+        for (int k = 0; k < 8; ++k) n_on[wave_simd[k]]++;
+        if (n_on[0] == 2 && n_on[1] == 2 && n_on[2] == 2 && n_on[3] == 2) {
+            const int w = tid >> 6, sm = wave_simd[w], p = (blockIdx.x >> 8) & 1;
+            int rank = 0;  // 0 for the first of the SIMD's two waves, 1 for the second
+            for (int k = 0; k < w; ++k) rank += wave_simd[k] == sm;
+            const int role = (sm >> 1) == p ? 2 * (sm & 1) + rank : 4 + (sm & 1) + 2 * rank;
+            vt = role * 64 + (tid & 63);
+        }
+    }
     const int TPQ = T / NQ;
-    const int q = tid % NQ, gs = tid / NQ;
+    const int q = vt % NQ, gs = vt / NQ;
     const bool on = gs < TPQ;
     uint32_t valid = 0;
     for (int i = 0; i < 4; ++i) valid |= (4 * q + i < nT ? 0xFFu : 0u) << (8 * i);
