@@ -232,6 +232,9 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         I.b32[i] = A.beta32[d.slot_off + i];
         I.b64[i] = A.beta[d.slot_off + i];
     }
+    // padding walkers of the last quad read slot 0's constants (never used:
+    // their bytes are never flipped or tallied)
+    for (int i = nT + tid; i < 4 * NQ; i += T) I.sow[i] = 0;
     __syncthreads();
 
     // thread -> (quad, first site group); threads beyond NQ * TPQ stay idle.
@@ -288,7 +291,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         int ts[4];
         for (int i = 0; i < 4; ++i) {
             const int w = 4 * q + i;
-            ts[i] = w < nT ? I.sow[w] : 0;
+            ts[i] = I.sow[w];  // (padding walkers: slot 0)
             const float cp = two_beta_log2e(I.b32[ts[i]]);
             ln.ka[i] = cp * 0x1p-18f;
             ln.kb[i] = cp * (d.h32 - (float)d.hgrid * 0x1p-18f);
@@ -323,8 +326,40 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
         // first (byte counters as 16-bit lanes, walkers 0 and 2 in one word,
         // 1 and 3 in another); lane j of the row then adds walker (j / NQ) mod
         // 4 of quad j mod NQ, so a wave issues three LDS atomics, not twelve.
-        const long long hg1 = 2 * (long long)hg + 1;
-        if (T >= 256 && NQ <= 4 && NQ != 3) {
+        // With NQ = 4 and at most five site groups per thread and half-sweep
+        // (any team size), the four lanes of a quad's residue class sum in
+        // narrower words: byte counters stay bytes (at most 4 x 2 x 4 x 5 =
+        // 160 flips) and the energy tallies stay int32 (at most 4 x 4 x 5 = 80
+        // sites of |(S_u + hgrid) XOR m'| <= 12 2^21 + 1, below 2^31).
+        const int hg1 = 2 * hg + 1;  // |hgrid| <= 6 2^21
+        if (NQ == 4 && 5 * TPQ >= G4) {
+            int cf = (int)ty.flips, cd = (int)ty.fdown, cn = (int)ty.nd;
+            cf += row_rotate<4>(cf);
+            cd += row_rotate<4>(cd);
+            cn += row_rotate<4>(cn);
+            cf += row_rotate<8>(cf);
+            cd += row_rotate<8>(cd);
+            cn += row_rotate<8>(cn);
+            int e[4];
+            for (int i = 0; i < 4; ++i) {
+                e[i] = ty.accE[i];
+                e[i] += row_rotate<4>(e[i]);
+                e[i] += row_rotate<8>(e[i]);
+            }
+            int tl = tid;
+            asm volatile("" : "+v"(tl));
+            const int sel = (tl >> 2) & 3, w = 4 * (tl & 3) + sel, sh = 8 * sel;
+            const int fl = (int)(((uint32_t)cf >> sh) & 0xFFu);
+            const int fd = (int)(((uint32_t)cd >> sh) & 0xFFu);
+            const int nd = (int)(((uint32_t)cn >> sh) & 0xFFu);
+            const int ea = sel == 0 ? e[0] : sel == 1 ? e[1] : sel == 2 ? e[2] : e[3];
+            const int t = sel == 0 ? ts[0] : sel == 1 ? ts[1] : sel == 2 ? ts[2] : ts[3];
+            if (w < nT) {
+                atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)((long long)ea + (long long)hg1 * nd));
+                atomicAdd(&I.dM[w], -2 * (fl - 2 * fd));
+                atomicAdd(&I.fl[t], fl);
+            }
+        } else if (T >= 256 && NQ <= 4 && NQ != 3) {
             uint32_t c[6] = {ty.flips & 0x00FF00FFu, (ty.flips >> 8) & 0x00FF00FFu,
                              ty.fdown & 0x00FF00FFu, (ty.fdown >> 8) & 0x00FF00FFu,
                              ty.nd & 0x00FF00FFu,    (ty.nd >> 8) & 0x00FF00FFu};
@@ -344,7 +379,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
             const long long ea = sel == 0 ? e[0] : sel == 1 ? e[1] : sel == 2 ? e[2] : e[3];
             const int t = sel == 0 ? ts[0] : sel == 1 ? ts[1] : sel == 2 ? ts[2] : ts[3];
             if (j < 4 * NQ && w < nT) {
-                atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)(ea + hg1 * nd));
+                atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)(ea + (long long)hg1 * nd));
                 atomicAdd(&I.dM[w], -2 * (fl - 2 * fd));
                 atomicAdd(&I.fl[t], fl);
             }
@@ -354,7 +389,7 @@ __device__ __forceinline__ void run_group_item(const SweepArgs &A, const SampleD
                 if (w < nT) {
                     const int fl = (int)((ty.flips >> (8 * i)) & 0xFFu), fd = (int)((ty.fdown >> (8 * i)) & 0xFFu);
                     const int nd = (int)((ty.nd >> (8 * i)) & 0xFFu);
-                    atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)(ty.accE[i] + hg1 * nd));
+                    atomicAdd((unsigned long long *)&I.dEJ[w], (unsigned long long)(ty.accE[i] + (long long)hg1 * nd));
                     atomicAdd(&I.dM[w], -2 * (fl - 2 * fd));
                     atomicAdd(&I.fl[ts[i]], fl);
                 }

@@ -202,9 +202,13 @@ __device__ __forceinline__ int row_rotate(int v)
 template <int K>
 __device__ __forceinline__ long long row_rotate(long long v)
 {
-    const unsigned lo = (unsigned)row_rotate<K>((int)(unsigned long long)v);
-    const unsigned hi = (unsigned)row_rotate<K>((int)((unsigned long long)v >> 32));
-    return (long long)(((unsigned long long)hi << 32) | lo);
+    // (the halves as a register pair: assembled with shifts and ors, the
+    // compiler adds the halves into a sum one at a time)
+    typedef int int2v __attribute__((ext_vector_type(2)));
+    int2v h = __builtin_bit_cast(int2v, v);
+    h.x = row_rotate<K>(h.x);
+    h.y = row_rotate<K>(h.y);
+    return __builtin_bit_cast(long long, h);
 }
 
 // Sum of v over the lanes of this lane's row of 16 whose index agrees with
