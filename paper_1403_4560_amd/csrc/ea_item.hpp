@@ -211,6 +211,42 @@ __device__ __forceinline__ long long row_rotate(long long v)
     return __builtin_bit_cast(long long, h);
 }
 
+// v of lane (this lane XOR K) within its aligned group of four (K = 1 or 2).
+template <int K>
+__device__ __forceinline__ int quad_xor(int v)
+{
+    static_assert(K == 1 || K == 2, "quad permutation");
+    return __builtin_amdgcn_mov_dpp(v, K == 1 ? 0xB1 : 0x4E, 0xF, 0xF, true);
+}
+
+template <int K>
+__device__ __forceinline__ long long quad_xor(long long v)
+{
+    typedef int int2v __attribute__((ext_vector_type(2)));
+    int2v h = __builtin_bit_cast(int2v, v);
+    h.x = quad_xor<K>(h.x);
+    h.y = quad_xor<K>(h.y);
+    return __builtin_bit_cast(long long, h);
+}
+
+// Sum over aligned groups of W = 4 or 16 consecutive lanes, every lane of the
+// group active (DPP: permutations within four lanes, rotations within a row).
+template <int W, class V>
+__device__ __forceinline__ V group_sum_dpp(V v)
+{
+    static_assert(W == 4 || W == 16, "group of four lanes or a row");
+    if constexpr (W == 4) {
+        v += quad_xor<1>(v);
+        v += quad_xor<2>(v);
+    } else {
+        v += row_rotate<8>(v);
+        v += row_rotate<4>(v);
+        v += row_rotate<2>(v);
+        v += row_rotate<1>(v);
+    }
+    return v;
+}
+
 // Sum of v over the lanes of this lane's row of 16 whose index agrees with
 // this lane's modulo S (S = 1, 2, 4, 8 or 16, uniform): rotations by S, 2S,
 // .., 8.  Every lane of the wave must be active.

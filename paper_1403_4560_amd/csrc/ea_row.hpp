@@ -414,11 +414,16 @@ __device__ __forceinline__ void run_item(const SweepArgs &A, const SampleDev &d,
                 else row_half_sweep<L, 1, 1>(A, d, r, n, I, rw_w, rw_y, rw_k, t, accE, nd, bf, bd);
                 // accE + nd = sum of s' (S_u + hgrid) over this thread's 4 L odd
                 // sites, |accE| <= 64 sites x 12 2^21 < 2^31; less hgrid sum s'
-                const long long sE =
-                    group_sum_i64<CPW>((long long)accE + nd - (long long)d.hgrid * (4 * L - 2 * nd));
-                const int sf = group_sum_i32<CPW>(bf), sd = group_sum_i32<CPW>(bd);
+                // leaves sum s' S_u, at most 4 L x 6 2^21 in size per thread:
+                // a group of four threads (L = 8) sums it in int32 (128 sites
+                // x 6 2^21 < 2^31), a row of sixteen (L = 16) in int64.
+                const long long own = (long long)accE + nd - (long long)d.hgrid * (4 * L - 2 * nd);
+                long long sE;
+                if constexpr (CPW == 4) sE = group_sum_dpp<CPW>((int)own);
+                else sE = group_sum_dpp<CPW>(own);
+                const int sf = group_sum_dpp<CPW>(bf), sd = group_sum_dpp<CPW>(bd);
                 if (rw_rem == 0) {
-                    const int flips = sf / 7, ndown = sd / 7;
+                    const int flips = (int)((unsigned)sf / 7u), ndown = (int)((unsigned)sd / 7u);
                     // dEJ collects minus the new E_J (both waves of the walker add)
                     atomicAdd((unsigned long long *)&I.dEJ[rw_w], (unsigned long long)sE);
                     atomicAdd(&I.dM[rw_w], -2 * (flips - 2 * ndown));
