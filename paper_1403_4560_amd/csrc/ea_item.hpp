@@ -81,27 +81,6 @@ __device__ __forceinline__ int wave_sum_i32(int v)
     return v;
 }
 
-// Sum over aligned groups of W consecutive lanes (W a power of two <= 64).
-template <int W>
-__device__ __forceinline__ long long group_sum_i64(long long v)
-{
-#pragma unroll
-    for (int m = W / 2; m >= 1; m >>= 1) {
-        const int lo = __shfl_xor((int)(unsigned long long)v, m);
-        const int hi = __shfl_xor((int)((unsigned long long)v >> 32), m);
-        v += (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-    }
-    return v;
-}
-
-template <int W>
-__device__ __forceinline__ int group_sum_i32(int v)
-{
-#pragma unroll
-    for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-    return v;
-}
-
 // Pointers into the dynamic LDS of one work item.
 struct ItemLds {
     int8_t *S;
