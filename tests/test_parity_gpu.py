@@ -165,6 +165,40 @@ def test_group_engine_quads_and_fields(torch_cuda):
     check(pm1, 10, splits=[4, 6])
 
 
+def test_group_engine_tally_forms(torch_cuda):
+    """The group engine sums its per-walker tallies in one of three forms: four
+    quads with at most five site groups per thread and half-sweep (bytes and
+    int32 over a residue class of four lanes), other teams of four or more
+    waves with one, two or four quads (16-bit lanes and int64 over a row of
+    16), and per thread otherwise.  L = 14 with 16 and 13 temperatures (three
+    site groups per thread, padding walkers in the last quad) takes the first,
+    L = 12 with 6 temperatures (two quads) the second on teams of 256 or more
+    threads, L = 12 with 10 (three quads) the third, L = 10 with 16 the first
+    or the third by team size; under every team plan the batch launch allows
+    (and per class launch) each equals the oracle bit for bit."""
+    from paper_1403_4560_amd import binding
+    work = W.make_workload([14, 14, 12, 12, 10], [16, 13, 6, 10, 16], (0.5, 1.6), [0.1, 0.2, 0.3, -0.1, 0.2],
+                           measure_every=3, measure_start=1, name="tally forms")
+    sweeps = 9
+    ref = O.OracleEnsemble(work).run(sweeps)
+    with binding.Ensemble(work) as ens:
+        assert ens.get_plan().batch == 1
+        variants = batch_variants(ens)
+    for teams in variants + [None]:
+        print("case: tally forms, batch plan", teams, flush=True)
+        with binding.Ensemble(work) as ens:
+            if teams is None:
+                ens.set_plan(batch=False)
+            else:
+                ens.set_batch_plan(teams)
+            ens.set_plan(chunk=4)
+            ens.sweep_pt(sweeps)
+            st = ens.read_state()
+            ms = ens.measure()
+            assert ens.check_energies() == 0
+        assert_same(work, st, ms, ref)
+
+
 def test_group_engine_unbatched(torch_cuda):
     work = W.config_workload("mixed_L6_12", samples=[0, 2, 3], measure_start=4)
     check(work, 16, unbatched=True)
