@@ -306,8 +306,8 @@ EA_HBM(32)
 
 // ---------------------------------------------------------------------------
 // Overlap measurement (eq. 2).  One wave per (sample, slot).  For each snapshot
-// frame of the chunk, in time order: the overlap bits e = NOT(a XOR b) of the
-// two chains' rows mark q_i = +1; the column counts
+// frame of the chunk: the overlap bits e = NOT(a XOR b) of the two chains'
+// rows mark q_i = +1; the column counts
 //   C[x][y] = #{z : e(x,y,z)},  D[x][z] = #{y : e(x,y,z)},  R[y][z] = #{x : e}
 // give the count of q_i = +1 in every plane of the nine wave vectors
 // k_f = (2 pi / L) u_f (each plane c = u_f . r mod L holds L^2 sites), so the
@@ -315,18 +315,22 @@ EA_HBM(32)
 // q(k_f) = sum_c P_f[c] e^{2 pi i c / L} / N (summed in c order), added to the
 // binary64 accumulators of the slot in time order.
 //
-// C and D come from bit-sliced vertical counters: lane y (C) adds the rows
-// (y, z) over z, lane 32 + z (D) the rows (y, z) over y, one 32-bit word per
-// step into six bit planes, and then reads the L column counts off the
-// planes.  Tables in LDS use a row stride of L + 1 words, so that the strided
-// reads of the plane sums fall in distinct banks.
+// A wave may take F frames side by side, one per group of G = 64 / F lanes,
+// each group at least 2 L lanes wide: the frames' counts and Fourier sums are
+// independent, and their accumulation stays one frame after the other.
+//
+// C and D come from bit-sliced vertical counters: lane y of a group (C) adds
+// the rows (y, z) over z, lane L + z (D) the rows (y, z) over y, one 32-bit
+// word per step into six bit planes, and then reads the L column counts off
+// the planes.  Tables in LDS use a row stride of L + 1 words, so that the
+// strided reads of the plane sums fall in distinct banks.
 template <int L>
 __device__ __forceinline__ void column_counts(const uint32_t *eqr, int lane, int *C, int *D)
 {
     constexpr int LP = L + 1;
-    const bool isC = lane < L, isD = lane >= 32 && lane - 32 < L;
+    const bool isC = lane < L, isD = lane >= L && lane < 2 * L;
     if (!isC && !isD) return;
-    const int u = isC ? lane : lane - 32;
+    const int u = isC ? lane : lane - L;
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
 #pragma unroll 4
     for (int v = 0; v < L; ++v) {
@@ -352,43 +356,47 @@ __device__ __forceinline__ void column_counts(const uint32_t *eqr, int lane, int
     }
 }
 
-// LDS of one slot's measurement.
+// Frames measured side by side by one wave of the per-size kernel: as many as
+// groups of 2 L lanes fit, at most two (four groups of 16 lanes, at L <= 8,
+// measured slower than two).
 template <int L>
+constexpr int meas_frames()
+{
+    return 2 * L <= 32 ? 2 : 1;
+}
+
+// LDS of one slot's measurement (per frame group g: the tables of its frame).
+template <int L, int F>
 struct MeasLds {
-    static constexpr int LP = L + 1, GC = 64 / L;  // GC: chunks of v per plane count
+    static_assert(F >= 1 && 2 * L * F <= 64, "a group of 2 L lanes per frame");
+    static constexpr int LP = L + 1, G = 64 / F;
+    static constexpr int GC = G / L;  // chunks of v per plane count
     double accs[NACC];
-    double re_f[NPLANE], im_f[NPLANE];
+    double re_f[F][NPLANE], im_f[F][NPLANE];
+    double Ea[F], Eb[F];
     double cst[L], snt[L];  // cos and sin of 2 pi c / L
-    uint32_t eqr[L * LP];
-    int C[L * LP], D[L * LP], R[L * LP];
-    int P[NPLANE][L];
-    int part[NPLANE][GC][L];
+    uint32_t eqr[F][L * LP];
+    int C[F][L * LP], D[F][L * LP], R[F][L * LP];
+    int P[F][NPLANE][L];
+    int part[F][NPLANE][GC][L];
 };
 
 // The measurement of slot A.slots[slot_index] by one wave, with its LDS at buf.
-template <int L>
+template <int L, int F>
 __device__ __forceinline__ void measure_slot(const MeasureArgs &A, int slot_index, char *buf)
 {
     constexpr int L2 = L * L, LP = L + 1;
     constexpr uint32_t mask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
-    constexpr int GC = MeasLds<L>::GC;
-    MeasLds<L> &S = *reinterpret_cast<MeasLds<L> *>(buf);
-    auto &eqr = S.eqr;
-    auto &C = S.C;
-    auto &D = S.D;
-    auto &R = S.R;
-    auto &P = S.P;
-    auto &part = S.part;
+    using M = MeasLds<L, F>;
+    constexpr int G = M::G, GC = M::GC;
+    M &S = *reinterpret_cast<M *>(buf);
     auto &accs = S.accs;
-    auto &re_f = S.re_f;
-    auto &im_f = S.im_f;
-    auto &cst = S.cst;
-    auto &snt = S.snt;
     const int gs = A.slots[slot_index];
     const int s = A.slot_sample[gs];
     const SampleDev d = A.samples[s];
     const int t = gs - d.slot_off;
     const int tid = threadIdx.x, T = blockDim.x;
+    const int g = tid / G, lt = tid - g * G;  // frame group, lane within it
     int64_t nf;
     if (A.explicit_frames > 0) {
         nf = A.explicit_frames;
@@ -400,34 +408,38 @@ __device__ __forceinline__ void measure_slot(const MeasureArgs &A, int slot_inde
     if (nf <= 0) return;
     for (int i = tid; i < NACC; i += T) accs[i] = A.acc[(size_t)gs * NACC + i];
     for (int c = tid; c < L; c += T) {
-        cst[c] = A.costab[(size_t)L * MAX_L + c];
-        snt[c] = A.sintab[(size_t)L * MAX_L + c];
+        S.cst[c] = A.costab[(size_t)L * MAX_L + c];
+        S.snt[c] = A.sintab[(size_t)L * MAX_L + c];
     }
     constexpr double Nd = (double)(L2 * L);
-    for (int64_t f = 0; f < nf; ++f) {
-        const uint32_t *ra = A.frames + f * A.frame_words + d.frame_off + (size_t)t * L2;
-        const uint32_t *rb = ra + (size_t)d.n_T * L2;
-        // the frame's two energies, loaded early (used after the plane sums)
-        double Ea = 0.0, Eb = 0.0;
-        if (tid == NPLANE) {
-            const double *E = A.frameE + f * 2 * A.total_slots + 2 * (size_t)d.slot_off;
-            Ea = E[t];
-            Eb = E[d.n_T + t];
-        }
-        for (int i = tid; i < L2; i += T) {
-            const uint32_t e = ~(ra[i] ^ rb[i]) & mask;
-            const int y = i % L, z = i / L;
-            eqr[y + LP * z] = e;
-            R[y + LP * z] = __builtin_popcount(e);
+    for (int64_t f0 = 0; f0 < nf; f0 += F) {
+        const int64_t f = f0 + g;
+        const bool live = f < nf;  // the last batch may hold fewer than F frames
+        uint32_t *eqr = S.eqr[g];
+        int *C = S.C[g], *D = S.D[g], *R = S.R[g];
+        if (live) {
+            const uint32_t *ra = A.frames + f * A.frame_words + d.frame_off + (size_t)t * L2;
+            const uint32_t *rb = ra + (size_t)d.n_T * L2;
+            if (lt == NPLANE) {  // the frame's two energies (used by the accumulation)
+                const double *E = A.frameE + f * 2 * A.total_slots + 2 * (size_t)d.slot_off;
+                S.Ea[g] = E[t];
+                S.Eb[g] = E[d.n_T + t];
+            }
+            for (int i = lt; i < L2; i += G) {
+                const uint32_t e = ~(ra[i] ^ rb[i]) & mask;
+                const int y = i % L, z = i / L;
+                eqr[y + LP * z] = e;
+                R[y + LP * z] = __builtin_popcount(e);
+            }
         }
         __syncthreads();
-        column_counts<L>(eqr, tid, C, D);  // C[x][y] at x*LP + y, D[x][z] at x*LP + z
+        if (live) column_counts<L>(eqr, lt, C, D);  // C[x][y] at x*LP + y, D[x][z] at x*LP + z
         __syncthreads();
         // plane counts: lane (c, chunk) sums v = chunk, chunk + GC, ... of
         // every family (no divergence: the family loop is unrolled), then
         // (family, c) tasks add the GC chunk partials (integers: any order)
-        if (tid < L * GC) {
-            const int c = tid % L, chunk = tid / L;
+        if (live && lt < L * GC) {
+            const int c = lt % L, chunk = lt / L;
 #pragma unroll
             for (int fam = 0; fam < NPLANE; ++fam) {
                 int cnt = 0;
@@ -445,45 +457,54 @@ __device__ __forceinline__ void measure_slot(const MeasureArgs &A, int slot_inde
                     else if (fam == 7) cnt += R[v + LP * cm];  // y + z = c
                     else cnt += R[v + LP * vm];                // y - z = c
                 }
-                part[fam][chunk][c] = cnt;
+                S.part[g][fam][chunk][c] = cnt;
             }
         }
         __syncthreads();
-        for (int task = tid; task < NPLANE * L; task += T) {
-            const int fam = task / L, c = task - fam * L;
-            int cnt = 0;
-            for (int g = 0; g < GC; ++g) cnt += part[fam][g][c];
-            P[fam][c] = 2 * cnt - L2;
+        if (live) {
+            for (int task = lt; task < NPLANE * L; task += G) {
+                const int fam = task / L, c = task - fam * L;
+                int cnt = 0;
+                for (int k = 0; k < GC; ++k) cnt += S.part[g][fam][k][c];
+                S.P[g][fam][c] = 2 * cnt - L2;
+            }
         }
         __syncthreads();
-        if (tid < NPLANE) {
+        if (live && lt < NPLANE) {
             double re = 0.0, im = 0.0;
             for (int c = 0; c < L; ++c) {
-                re += (double)P[tid][c] * cst[c];
-                im += (double)P[tid][c] * snt[c];
+                re += (double)S.P[g][lt][c] * S.cst[c];
+                im += (double)S.P[g][lt][c] * S.snt[c];
             }
-            re_f[tid] = re / Nd;
-            im_f[tid] = im / Nd;
+            S.re_f[g][lt] = re / Nd;
+            S.im_f[g][lt] = im / Nd;
         }
         __syncthreads();
+        // the batch's frames into the accumulators, in time order
+        const int nb = nf - f0 < F ? (int)(nf - f0) : F;
         if (tid < NPLANE) {
-            const double re = re_f[tid], im = im_f[tid];
-            accs[5 + 3 * tid] += re;
-            accs[6 + 3 * tid] += im;
-            accs[7 + 3 * tid] += re * re + im * im;
+            for (int k = 0; k < nb; ++k) {
+                const double re = S.re_f[k][tid], im = S.im_f[k][tid];
+                accs[5 + 3 * tid] += re;
+                accs[6 + 3 * tid] += im;
+                accs[7 + 3 * tid] += re * re + im * im;
+            }
         } else if (tid == NPLANE) {
-            int S0 = 0;
-            for (int c = 0; c < L; ++c) S0 += P[0][c];
-            const double q0 = (double)S0 / Nd;
-            accs[0] += 1.0;
-            accs[1] += q0;
-            accs[2] += q0 * q0;
-            accs[3] += (q0 * q0) * q0;
-            accs[4] += (q0 * q0) * (q0 * q0);
-            accs[32] += Ea;
-            accs[33] += Ea * Ea;
-            accs[34] += Eb;
-            accs[35] += Eb * Eb;
+            for (int k = 0; k < nb; ++k) {
+                int S0 = 0;
+                for (int c = 0; c < L; ++c) S0 += S.P[k][0][c];
+                const double q0 = (double)S0 / Nd;
+                accs[0] += 1.0;
+                accs[1] += q0;
+                accs[2] += q0 * q0;
+                accs[3] += (q0 * q0) * q0;
+                accs[4] += (q0 * q0) * (q0 * q0);
+                const double Ea = S.Ea[k], Eb = S.Eb[k];
+                accs[32] += Ea;
+                accs[33] += Ea * Ea;
+                accs[34] += Eb;
+                accs[35] += Eb * Eb;
+            }
         }
         __syncthreads();
     }
@@ -493,18 +514,23 @@ __device__ __forceinline__ void measure_slot(const MeasureArgs &A, int slot_inde
 template <int L>
 __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
 {
-    __shared__ __attribute__((aligned(16))) char buf[sizeof(MeasLds<L>)];
-    measure_slot<L>(A, blockIdx.x, buf);
+    __shared__ __attribute__((aligned(16))) char buf[sizeof(MeasLds<L, meas_frames<L>()>)];
+    measure_slot<L, meas_frames<L>()>(A, blockIdx.x, buf);
 }
 
 // Every slot of lattice sizes up to 16 in one launch (one wave per slot, the
-// slot's own lattice size chosen per workgroup; LDS sized for L = 16).
+// slot's own lattice size chosen per workgroup; LDS sized for L = 16; one
+// frame at a time: with frames side by side the registers and LDS of the
+// largest size cut the residency of every size).
 __global__ void __launch_bounds__(64) measure_all_kernel(MeasureArgs A)
 {
-    __shared__ __attribute__((aligned(16))) char buf[sizeof(MeasLds<16>)];
+    __shared__ __attribute__((aligned(16))) char buf[sizeof(MeasLds<16, 1>)];
     const int L = A.samples[A.slot_sample[A.slots[blockIdx.x]]].L;
 #define EA_M(Lv) \
-    case Lv: measure_slot<Lv>(A, blockIdx.x, buf); break;
+    case Lv:                                                                              \
+        static_assert(sizeof(MeasLds<Lv, 1>) <= sizeof(MeasLds<16, 1>), "measurement LDS"); \
+        measure_slot<Lv, 1>(A, blockIdx.x, buf);                                          \
+        break;
     switch (L) {
         EA_M(2) EA_M(4) EA_M(6) EA_M(8) EA_M(10) EA_M(12) EA_M(14) EA_M(16)
     default: break;
