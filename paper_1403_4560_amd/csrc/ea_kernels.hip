@@ -320,17 +320,19 @@ EA_HBM(32)
 // independent, and their accumulation stays one frame after the other.
 //
 // C and D come from bit-sliced vertical counters: lane y of a group (C) adds
-// the rows (y, z) over z, lane L + z (D) the rows (y, z) over y, one 32-bit
-// word per step into six bit planes, and then reads the L column counts off
-// the planes.  Tables in LDS use a row stride of L + 1 words, so that the
-// strided reads of the plane sums fall in distinct banks.
-template <int L>
+// the rows (y, z) over z, lane D0 + z (D) the rows (y, z) over y (D0 = L
+// with frames side by side, else 32), one 32-bit word per step into six bit
+// planes, and then reads the L column counts off the planes.  Tables in LDS
+// use a row stride of L + 1 words, so that the strided reads of the plane
+// sums fall in distinct banks.
+template <int L, int D0>
 __device__ __forceinline__ void column_counts(const uint32_t *eqr, int lane, int *C, int *D)
 {
     constexpr int LP = L + 1;
-    const bool isC = lane < L, isD = lane >= L && lane < 2 * L;
+    static_assert(D0 >= L && D0 + L <= 64, "C and D lanes apart");
+    const bool isC = lane < L, isD = lane >= D0 && lane < D0 + L;
     if (!isC && !isD) return;
-    const int u = isC ? lane : lane - L;
+    const int u = isC ? lane : lane - D0;
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
 #pragma unroll 4
     for (int v = 0; v < L; ++v) {
@@ -417,13 +419,18 @@ __device__ __forceinline__ void measure_slot(const MeasureArgs &A, int slot_inde
         const bool live = f < nf;  // the last batch may hold fewer than F frames
         uint32_t *eqr = S.eqr[g];
         int *C = S.C[g], *D = S.D[g], *R = S.R[g];
+        double Ea = 0.0, Eb = 0.0;  // one frame per wave: the accumulating lane's own
         if (live) {
             const uint32_t *ra = A.frames + f * A.frame_words + d.frame_off + (size_t)t * L2;
             const uint32_t *rb = ra + (size_t)d.n_T * L2;
-            if (lt == NPLANE) {  // the frame's two energies (used by the accumulation)
+            if (lt == NPLANE) {  // the frame's two energies, loaded early (used by the accumulation)
                 const double *E = A.frameE + f * 2 * A.total_slots + 2 * (size_t)d.slot_off;
-                S.Ea[g] = E[t];
-                S.Eb[g] = E[d.n_T + t];
+                Ea = E[t];
+                Eb = E[d.n_T + t];
+                if constexpr (F > 1) {
+                    S.Ea[g] = Ea;
+                    S.Eb[g] = Eb;
+                }
             }
             for (int i = lt; i < L2; i += G) {
                 const uint32_t e = ~(ra[i] ^ rb[i]) & mask;
@@ -433,7 +440,7 @@ __device__ __forceinline__ void measure_slot(const MeasureArgs &A, int slot_inde
             }
         }
         __syncthreads();
-        if (live) column_counts<L>(eqr, lt, C, D);  // C[x][y] at x*LP + y, D[x][z] at x*LP + z
+        if (live) column_counts<L, F == 1 ? 32 : L>(eqr, lt, C, D);  // C[x][y] at x*LP + y, D[x][z] at x*LP + z
         __syncthreads();
         // plane counts: lane (c, chunk) sums v = chunk, chunk + GC, ... of
         // every family (no divergence: the family loop is unrolled), then
@@ -481,7 +488,7 @@ __device__ __forceinline__ void measure_slot(const MeasureArgs &A, int slot_inde
         }
         __syncthreads();
         // the batch's frames into the accumulators, in time order
-        const int nb = nf - f0 < F ? (int)(nf - f0) : F;
+        const int nb = F == 1 ? 1 : nf - f0 < F ? (int)(nf - f0) : F;
         if (tid < NPLANE) {
             for (int k = 0; k < nb; ++k) {
                 const double re = S.re_f[k][tid], im = S.im_f[k][tid];
@@ -499,11 +506,11 @@ __device__ __forceinline__ void measure_slot(const MeasureArgs &A, int slot_inde
                 accs[2] += q0 * q0;
                 accs[3] += (q0 * q0) * q0;
                 accs[4] += (q0 * q0) * (q0 * q0);
-                const double Ea = S.Ea[k], Eb = S.Eb[k];
-                accs[32] += Ea;
-                accs[33] += Ea * Ea;
-                accs[34] += Eb;
-                accs[35] += Eb * Eb;
+                const double ea = F == 1 ? Ea : S.Ea[k], eb = F == 1 ? Eb : S.Eb[k];
+                accs[32] += ea;
+                accs[33] += ea * ea;
+                accs[34] += eb;
+                accs[35] += eb * eb;
             }
         }
         __syncthreads();
