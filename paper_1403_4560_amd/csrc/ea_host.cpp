@@ -31,7 +31,6 @@ template <int L, int JK, int VAR> __global__ void hbm_half_kernel(SweepArgs A);
 __global__ void hbm_exchange_kernel(SweepArgs A);
 __global__ void hbm_snapshot_kernel(SweepArgs A);
 template <int L> __global__ void measure_kernel(MeasureArgs A);
-__global__ void measure_all_kernel(MeasureArgs A);
 __global__ void advance_kernel(int64_t *state, int64_t k);
 template <int JK> __global__ void batch_sweep_kernel(SweepArgs A, BatchArgs B);
 __global__ void exp_bracket_kernel(uint32_t, uint32_t, unsigned long long *, unsigned int *);
@@ -429,19 +428,6 @@ MeasureFn measure_fn(int L)
 // launch per lattice size, one wave per slot.
 hipError_t launch_measure(ea_ensemble *e, int K, int explicit_frames)
 {
-    // lattice sizes up to 16: one launch for every slot
-    bool small = true;
-    int total = 0;
-    for (const auto &c : e->slot_classes) {
-        small &= c.L <= LDS_MAX_L;
-        total += c.count;
-    }
-    if (small && e->slot_classes.size() > 1) {
-        MeasureArgs M = measure_args(e, K, explicit_frames);
-        M.slots = (const int32_t *)e->mslots.p;
-        hipLaunchKernelGGL(measure_all_kernel, dim3((unsigned)total), dim3(64), 0, e->stream, M);
-        return hipGetLastError();
-    }
     for (const auto &c : e->slot_classes) {
         MeasureArgs M = measure_args(e, K, explicit_frames);
         M.slots = (const int32_t *)e->mslots.p + c.begin;

@@ -358,9 +358,9 @@ __device__ __forceinline__ void column_counts(const uint32_t *eqr, int lane, int
     }
 }
 
-// Frames measured side by side by one wave of the per-size kernel: as many as
-// groups of 2 L lanes fit, at most two (four groups of 16 lanes, at L <= 8,
-// measured slower than two).
+// Frames measured side by side by one wave: as many as groups of 2 L lanes
+// fit, at most two (four groups of 16 lanes, at L <= 8, measured no faster
+// than one).
 template <int L>
 constexpr int meas_frames()
 {
@@ -523,26 +523,6 @@ __global__ void __launch_bounds__(64) measure_kernel(MeasureArgs A)
 {
     __shared__ __attribute__((aligned(16))) char buf[sizeof(MeasLds<L, meas_frames<L>()>)];
     measure_slot<L, meas_frames<L>()>(A, blockIdx.x, buf);
-}
-
-// Every slot of lattice sizes up to 16 in one launch (one wave per slot, the
-// slot's own lattice size chosen per workgroup; LDS sized for L = 16; one
-// frame at a time: with frames side by side the registers and LDS of the
-// largest size cut the residency of every size).
-__global__ void __launch_bounds__(64) measure_all_kernel(MeasureArgs A)
-{
-    __shared__ __attribute__((aligned(16))) char buf[sizeof(MeasLds<16, 1>)];
-    const int L = A.samples[A.slot_sample[A.slots[blockIdx.x]]].L;
-#define EA_M(Lv) \
-    case Lv:                                                                              \
-        static_assert(sizeof(MeasLds<Lv, 1>) <= sizeof(MeasLds<16, 1>), "measurement LDS"); \
-        measure_slot<Lv, 1>(A, blockIdx.x, buf);                                          \
-        break;
-    switch (L) {
-        EA_M(2) EA_M(4) EA_M(6) EA_M(8) EA_M(10) EA_M(12) EA_M(14) EA_M(16)
-    default: break;
-    }
-#undef EA_M
 }
 
 #define EA_MEAS(Lv) template __global__ void measure_kernel<Lv>(MeasureArgs);
